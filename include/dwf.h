@@ -1,0 +1,197 @@
+/*
+ * dwf.h -- C ABI of the MI355X (gfx950) domain-wall / Moebius hot path.
+ *
+ * Method: H. Yin and R. D. Mawhinney, "Improving DWF Simulations: the Force
+ * Gradient Integrator and the Moebius Accelerated DWF Solver", Lattice 2011.
+ *   Sec. 4  the Dirac equation D_DW(m) x = b, the Moebius operator D'_DW and
+ *           the Moebius-accelerated solver (MADWF);
+ *   Sec. 5  defect correction; Table 1 ("Op. count" = 4D Wilson applications);
+ *   Sec. 2  the force e_i(S), e_i(U) = T_i U, and the force-gradient step
+ *           U' = exp(-tau^2/24 F^j T_j) U with the first solve reused.
+ *
+ * Operator conventions (the paper defers the definitions to its
+ * domain-wall/overlap transformation reference; these are the readings used):
+ *   D_W psi(x) = (4 - M5) psi(x) - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *                                             + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)]
+ *   chiral basis, g_5 = diag(1, 1, -1, -1), P+- = (1 +- g_5)/2;
+ *   (D(m) psi)_s = (b D_W + 1) psi_s + (c D_W - 1)(P- psi_{s+1} + P+ psi_{s-1}),
+ *   psi_{Ls} = -m psi_0, psi_{-1} = -m psi_{Ls-1}; Shamir DWF is b = 1, c = 0.
+ *   Even-odd split on the 4D checkerboard, parity (x+y+z+t) mod 2:
+ *   D = [[A, B_eo], [B_oe, A]], A = (b d + 1) + (c d - 1) S~, d = 4 - M5,
+ *   B = -1/2 H (b + c S~), M_prec = 1 - A^-1 B_oe A^-1 B_eo (odd sites).
+ *
+ * Data layouts.  Every pointer argument named U, in, out, b, x, phi is a
+ * DEVICE pointer (hipMalloc / torch CUDA tensor) owned by the caller.
+ *   natural gauge   complex128 [4][T][Z][Y][X][3][3]   (mu = 0..3 <-> x,y,z,t)
+ *   natural 5D      complex128 [Ls][T][Z][Y][X][4][3]
+ *   natural force   complex128 [4][T][Z][Y][X][3][3]
+ *   packed half     one parity: [x_cb][12][Ls] pairs (re, im) of the storage
+ *                   type (fp64, fp32, fp16, bf16), x_cb = lexicographic index/2,
+ *                   component 12 = spin*3 + colour; fp16 adds a trailing
+ *                   float norm array [x_cb][Ls] (value = stored * norm).
+ *   packed full     [even half][odd half].
+ *   packed gauge    per output parity p: [x_cb][8][3][3] pairs: directions
+ *                   0..3 = U_mu(x), 4..7 = U_mu(x-mu)^+, antiperiodic phase
+ *                   folded in; parity 0 block then parity 1 block.
+ * dwf_field_bytes() gives the size of every packed layout.
+ *
+ * Ownership and streams: the library owns only what a dwf_ctx allocates
+ * (workspace, geometry tables, packed low-precision copies); it is freed by
+ * dwf_ctx_destroy.  All work is ordered on the ctx stream.  Solver calls
+ * return after the FP64 true residual has been read back to the host.
+ *
+ * Errors: every call returns DWF_OK (0), a negative error code, or
+ * DWF_NOT_CONVERGED (> 0, the info struct is still filled and x holds the
+ * best iterate).  dwf_last_error() returns a thread-local message for the
+ * last failing call.  No C++ exception crosses this interface.  A call
+ * whose arguments fail validation performs no device work.
+ */
+#ifndef DWF_H
+#define DWF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DWF_OK 0
+#define DWF_NOT_CONVERGED 1
+#define DWF_ERR_ARG (-1)   /* invalid extents, Ls, precision, op or NULL pointer */
+#define DWF_ERR_HIP (-2)   /* a HIP runtime error (message in dwf_last_error) */
+#define DWF_ERR_NOMEM (-3) /* device allocation failed */
+#define DWF_ERR_NAN (-4)   /* a NaN/Inf appeared in a source or a residual */
+
+enum dwf_precision { DWF_FP64 = 0, DWF_FP32 = 1, DWF_FP16 = 2, DWF_BF16 = 3 };
+enum dwf_kind { DWF_KIND_GAUGE = 0, DWF_KIND_FULL = 1, DWF_KIND_EVEN = 2, DWF_KIND_ODD = 3 };
+enum dwf_op {
+  DWF_OP_HOP = 0,   /* Wilson hop H (dwf_dslash) or H (b + c S~) (mobius_dslash), parity -> parity */
+  DWF_OP_MPREC = 1, /* M_prec on odd halves */
+  DWF_OP_FULL = 2,  /* D(m) on packed full fields */
+  DWF_OP_A = 3,     /* site-local A on a half field */
+  DWF_OP_AINV = 4   /* site-local A^-1 on a half field */
+};
+
+typedef struct {
+  int dims[4];    /* X, Y, Z, T: each even and >= 2 */
+  int Ls;         /* fifth-dimension extent, 2..128 */
+  int tbc;        /* 0 periodic, 1 antiperiodic in T */
+  double M5;      /* domain-wall height (D_W at mass -M5) */
+  double mass;    /* quark mass m (1.0 = Pauli-Villars) */
+  double b, c;    /* Moebius coefficients (Shamir: 1, 0) */
+  int prec;       /* storage precision of packed operands of dslash calls */
+  int prec_inner; /* inner-iteration precision of solvers (FP64 = plain FP64 CG) */
+} dwf_params;
+
+typedef struct {
+  /* in */
+  double tol;      /* target full-system true residual ||b - D x|| / ||b|| */
+  double delta;    /* reliable-update trigger: iterated residual fell by this factor (0 -> 0.1) */
+  int maxit;       /* iteration cap over all restarts (0 -> 100000) */
+  /* out */
+  int iters;                /* CG iterations (each one M_prec^+ M_prec application) */
+  int reliable_updates;     /* FP64 residual recomputations */
+  int restarts;             /* tightenings of the normal-equation tolerance */
+  double true_rel_resid;    /* FP64 ||b - D x|| / ||b|| on return */
+  double seconds;           /* wall time of the call */
+  long long wilson_apps;    /* Table 1 "Op. count": iterations x Ls */
+  int iters_first;          /* fermion_force with tau_fg > 0: iterations of the solve at U */
+} dwf_solve_info;
+
+typedef struct {
+  /* in */
+  int n_dc;           /* defect-correction steps (Sec. 5; the paper uses 3) */
+  double tol_pv;      /* relative tolerance of the Pauli-Villars solves */
+  double tol_mobius;  /* relative tolerance of the Moebius solve */
+  double tol;         /* final full-system true residual */
+  double delta;       /* reliable-update trigger (0 -> 0.1) */
+  int maxit;          /* cap per solve (0 -> 100000) */
+  int prec_pv;        /* inner precision of the PV solves */
+  int prec_final;     /* inner precision of the final DWF solve */
+  /* out */
+  int pv_iters, mobius_iters, final_iters, n_pv, n_mobius;
+  double resid_after_dc[8];
+  double true_rel_resid;
+  double seconds, seconds_pv, seconds_mobius, seconds_final;
+  long long wilson_apps; /* pv_iters*L + mobius_iters*L' + final_iters*L */
+} dwf_madwf_info;
+
+typedef struct dwf_ctx dwf_ctx;
+
+/* Create a context bound to a HIP stream (hipStream_t as void*; NULL = the
+ * default stream) on the current device. */
+int dwf_ctx_create(dwf_ctx** ctx, void* stream);
+int dwf_ctx_destroy(dwf_ctx* ctx);
+int dwf_ctx_set_stream(dwf_ctx* ctx, void* stream);
+const char* dwf_last_error(void);
+
+/* Bytes of a packed field of the given kind and precision (0 on bad arguments). */
+size_t dwf_field_bytes(const dwf_params* p, int kind, int prec);
+
+/* natural (complex128, device) <-> packed (device).  EVEN/ODD pack reads the
+ * sites of that parity from a natural 5D field; unpack writes only them.
+ * Gauge pack folds the boundary phase and the backward daggers in. */
+int dwf_pack(dwf_ctx* ctx, const dwf_params* p, int kind, int prec, const void* natural, void* packed);
+int dwf_unpack(dwf_ctx* ctx, const dwf_params* p, int kind, int prec, const void* packed, void* natural);
+/* packed -> packed precision conversion (round to nearest even). */
+int dwf_convert(dwf_ctx* ctx, const dwf_params* p, int kind, int prec_in, const void* in, int prec_out,
+                void* out);
+
+/* One application of the Shamir DWF operator family (b, c ignored: 1, 0) on packed
+ * operands of precision p->prec (Sec. 4, D_DW(m); the hop is the paper's unit of
+ * cost, Table 1).  op HOP: out (parity `parity`) = H in (other parity); MPREC:
+ * odd -> odd; FULL: D(m) on full fields; A / AINV: site-local blocks.
+ * dagger = 1 applies the adjoint.  in and out must not alias. */
+int dwf_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op, int parity,
+               int dagger);
+
+/* The same for the Moebius operator D'_DW(m) with p->b, p->c (Sec. 4); op HOP
+ * applies H (b + c S~). */
+int mobius_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op,
+                  int parity, int dagger);
+
+/* Solve D(m) x = b (Sec. 4, the Dirac equation) for packed FP64 full fields by
+ * CG on the even-odd normal equations.  U: packed FP64 gauge.  x holds the
+ * initial guess on entry.  p->prec_inner < FP64 runs the iterations in that
+ * storage precision (FP32 arithmetic) with FP64 reliable updates, FP64 CG
+ * scalars and an FP64 solution accumulator. */
+int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info);
+
+/* Several right-hand sides of one lattice (per-RHS mass: the Hasenbusch ladder
+ * of Sec. 3) in one batched solve: each CG iteration applies the operator to
+ * all unconverged RHS with a single kernel launch per hop that loads every
+ * link once for all of them.  per_rhs[k] may differ only in mass; b[k], x[k]
+ * are packed FP64 full fields. */
+int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void* U, const void* const* b,
+                  void* const* x, dwf_solve_info* per_rhs_info);
+
+/* Moebius-accelerated DWF solve (Sec. 4 algorithm, Sec. 5 defect correction):
+ * target = Shamir DWF (Ls = L), inner = Moebius (Ls = L', b', c', same dims,
+ * M5, mass).  info->n_dc steps of: residual, PV solve, Moebius solve, PV
+ * reconstruction; then a warm-started DWF solve to info->tol.  x is
+ * overwritten (packed FP64 full, target Ls). */
+int mobius_accel_solve(dwf_ctx* ctx, const dwf_params* target, const dwf_params* inner, const void* U,
+                       const void* b, void* x, dwf_madwf_info* info);
+
+/* Fermion force of S = phi^+ (M_prec^+ M_prec)^-1 phi (Sec. 2: e_i(S) with
+ * e_i(U) = T_i U, T_a = i lambda_a / 2).  phi: packed FP64 odd half.  x_io:
+ * optional packed FP64 odd half: initial guess in, X = (M^+M)^-1 phi out.
+ * F (device, natural force layout, complex128) receives
+ *   out_kind 0: F_mu(x) = sum_a e_a(S) T_a                (traceless anti-Hermitian)
+ *   out_kind 1: G_mu(x) = dS/dU in the convention dS = Re sum conj(G) dU.
+ * tau_fg > 0: force-gradient step -- F1 at U, U' = exp(-tau^2/24 F1) U, then the
+ * force at U' with its solve started from X(U); U is left unchanged.
+ * *S receives the action at the configuration whose force is returned. */
+int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U_natural, const void* phi, void* F, double* S,
+                  double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
+
+/* Set / query the launch configuration of the hop kernels (sites per block and
+ * s-values per thread); used by the autotuner.  kernel_id 0 = hop.  A zero
+ * config restores the built-in default. */
+int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_block, int s_per_thread);
+int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* sites_per_block, int* s_per_thread);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DWF_H */

@@ -1,0 +1,241 @@
+"""MI355X (gfx950) domain-wall / Moebius hot path: Python binding of libdwf.so.
+
+A thin ctypes layer over the C ABI declared in ``include/dwf.h``; every step
+of the computation runs in the HIP kernels of the library.  PyTorch supplies
+device memory and the stream; tensors are passed by ``data_ptr()``.  If the
+library is not built, importing works but every call raises.
+
+Method: Yin & Mawhinney, "Improving DWF Simulations: the Force Gradient
+Integrator and the Moebius Accelerated DWF Solver", Lattice 2011 (Secs. 2, 4, 5).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdwf.so")
+
+DWF_OK, DWF_NOT_CONVERGED = 0, 1
+DWF_ERR_ARG, DWF_ERR_HIP, DWF_ERR_NOMEM, DWF_ERR_NAN = -1, -2, -3, -4
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+KIND_GAUGE, KIND_FULL, KIND_EVEN, KIND_ODD = 0, 1, 2, 3
+OP_HOP, OP_MPREC, OP_FULL, OP_A, OP_AINV = 0, 1, 2, 3, 4
+PREC_NAMES = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+
+
+class DwfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dwf error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("Ls", ctypes.c_int), ("tbc", ctypes.c_int),
+                ("M5", ctypes.c_double), ("mass", ctypes.c_double), ("b", ctypes.c_double),
+                ("c", ctypes.c_double), ("prec", ctypes.c_int), ("prec_inner", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("delta", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("true_rel_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("wilson_apps", ctypes.c_longlong), ("iters_first", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MadwfInfo(ctypes.Structure):
+    _fields_ = [("n_dc", ctypes.c_int), ("tol_pv", ctypes.c_double), ("tol_mobius", ctypes.c_double),
+                ("tol", ctypes.c_double), ("delta", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("prec_pv", ctypes.c_int), ("prec_final", ctypes.c_int),
+                ("pv_iters", ctypes.c_int), ("mobius_iters", ctypes.c_int), ("final_iters", ctypes.c_int),
+                ("n_pv", ctypes.c_int), ("n_mobius", ctypes.c_int),
+                ("resid_after_dc", ctypes.c_double * 8), ("true_rel_resid", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("seconds_pv", ctypes.c_double),
+                ("seconds_mobius", ctypes.c_double), ("seconds_final", ctypes.c_double),
+                ("wilson_apps", ctypes.c_longlong)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "resid_after_dc"}
+        d["resid_after_dc"] = [self.resid_after_dc[i] for i in range(max(0, min(self.n_dc, 8)))]
+        return d
+
+
+_lib = None
+
+# exported symbols of include/dwf.h with their ctypes signatures
+_vp, _ci, _cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+_PP = ctypes.POINTER(Params)
+SIGNATURES = {
+    "dwf_ctx_create": ([ctypes.POINTER(_vp), _vp], _ci),
+    "dwf_ctx_destroy": ([_vp], _ci),
+    "dwf_ctx_set_stream": ([_vp, _vp], _ci),
+    "dwf_last_error": ([], ctypes.c_char_p),
+    "dwf_field_bytes": ([_PP, _ci, _ci], ctypes.c_size_t),
+    "dwf_pack": ([_vp, _PP, _ci, _ci, _vp, _vp], _ci),
+    "dwf_unpack": ([_vp, _PP, _ci, _ci, _vp, _vp], _ci),
+    "dwf_convert": ([_vp, _PP, _ci, _ci, _vp, _ci, _vp], _ci),
+    "dwf_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
+    "mobius_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
+    "cg_ne": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)], _ci),
+    "cg_ne_batched": ([_vp, _ci, _PP, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(SolveInfo)], _ci),
+    "mobius_accel_solve": ([_vp, _PP, _PP, _vp, _vp, _vp, ctypes.POINTER(MadwfInfo)], _ci),
+    "fermion_force": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(_cd), _cd, _ci, _vp, ctypes.POINTER(SolveInfo)], _ci),
+    "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci], _ci),
+    "dwf_tune_get": ([_vp, _ci, _ci, _ci, ctypes.POINTER(_ci), ctypes.POINTER(_ci)], _ci),
+}
+
+
+def lib():
+    """Load libdwf.so (built by paper_1111_5059_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DwfError(DWF_ERR_ARG, f"{LIB_PATH} is not built: run python -m paper_1111_5059_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow_not_converged=False):
+    if rc == DWF_OK or (allow_not_converged and rc == DWF_NOT_CONVERGED):
+        return rc
+    msg = lib().dwf_last_error()
+    raise DwfError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def params(dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0, prec=FP64, prec_inner=FP64):
+    p = Params()
+    for k in range(4):
+        p.dims[k] = int(dims[k])
+    p.Ls, p.tbc = int(Ls), int(tbc)
+    p.M5, p.mass, p.b, p.c = float(M5), float(mass), float(b), float(c)
+    p.prec, p.prec_inner = int(prec), int(prec_inner)
+    return p
+
+
+class Context:
+    """Owns a dwf_ctx bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.handle = _vp()
+        _check(lib().dwf_ctx_create(ctypes.byref(self.handle), _vp(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().dwf_ctx_destroy(self.handle)
+            self.handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dwf_ctx_create(stream=None):
+    return Context(stream)
+
+
+def dwf_field_bytes(p, kind, prec):
+    return lib().dwf_field_bytes(ctypes.byref(p), int(kind), int(prec))
+
+
+def dwf_pack(ctx, p, kind, prec, natural, packed):
+    _check(lib().dwf_pack(ctx.handle, ctypes.byref(p), int(kind), int(prec), _vp(_ptr(natural)), _vp(_ptr(packed))))
+
+
+def dwf_unpack(ctx, p, kind, prec, packed, natural):
+    _check(lib().dwf_unpack(ctx.handle, ctypes.byref(p), int(kind), int(prec), _vp(_ptr(packed)), _vp(_ptr(natural))))
+
+
+def dwf_convert(ctx, p, kind, prec_in, src, prec_out, dst):
+    _check(lib().dwf_convert(ctx.handle, ctypes.byref(p), int(kind), int(prec_in), _vp(_ptr(src)),
+                             int(prec_out), _vp(_ptr(dst))))
+
+
+def dwf_dslash(ctx, p, U, src, dst, op, parity=0, dagger=False):
+    _check(lib().dwf_dslash(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(src)), _vp(_ptr(dst)),
+                            int(op), int(parity), int(bool(dagger))))
+
+
+def mobius_dslash(ctx, p, U, src, dst, op, parity=0, dagger=False):
+    _check(lib().mobius_dslash(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(src)), _vp(_ptr(dst)),
+                               int(op), int(parity), int(bool(dagger))))
+
+
+def cg_ne(ctx, p, U, b, x, tol=1e-10, delta=0.1, maxit=100000):
+    info = SolveInfo()
+    info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
+    rc = _check(lib().cg_ne(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(b)), _vp(_ptr(x)),
+                            ctypes.byref(info)), allow_not_converged=True)
+    d = info.as_dict()
+    d["converged"] = rc == DWF_OK
+    return d
+
+
+def cg_ne_batched(ctx, per_rhs, U, bs, xs, tol=1e-10, delta=0.1, maxit=100000):
+    n = len(per_rhs)
+    P = (Params * n)(*per_rhs)
+    B = (_vp * n)(*[_ptr(b) for b in bs])
+    X = (_vp * n)(*[_ptr(x) for x in xs])
+    infos = (SolveInfo * n)()
+    for k in range(n):
+        infos[k].tol, infos[k].delta, infos[k].maxit = float(tol), float(delta), int(maxit)
+    rc = _check(lib().cg_ne_batched(ctx.handle, n, P, _vp(_ptr(U)), B, X, infos), allow_not_converged=True)
+    out = [infos[k].as_dict() for k in range(n)]
+    for d in out:
+        d["converged"] = d["true_rel_resid"] <= tol
+    return out
+
+
+def mobius_accel_solve(ctx, target, inner, U, b, x, n_dc=3, tol_pv=1e-8, tol_mobius=1e-5, tol=1e-10,
+                       delta=0.1, maxit=100000, prec_pv=FP32, prec_final=FP32):
+    info = MadwfInfo()
+    info.n_dc, info.tol_pv, info.tol_mobius, info.tol = int(n_dc), float(tol_pv), float(tol_mobius), float(tol)
+    info.delta, info.maxit, info.prec_pv, info.prec_final = float(delta), int(maxit), int(prec_pv), int(prec_final)
+    rc = _check(lib().mobius_accel_solve(ctx.handle, ctypes.byref(target), ctypes.byref(inner), _vp(_ptr(U)),
+                                         _vp(_ptr(b)), _vp(_ptr(x)), ctypes.byref(info)), allow_not_converged=True)
+    d = info.as_dict()
+    d["converged"] = rc == DWF_OK
+    return d
+
+
+def fermion_force(ctx, p, U_natural, phi, F, tau_fg=0.0, out_kind=0, x_io=None, tol=1e-12, delta=0.1,
+                  maxit=100000):
+    info = SolveInfo()
+    info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
+    S = ctypes.c_double(0.0)
+    _check(lib().fermion_force(ctx.handle, ctypes.byref(p), _vp(_ptr(U_natural)), _vp(_ptr(phi)), _vp(_ptr(F)),
+                               ctypes.byref(S), float(tau_fg), int(out_kind), _vp(_ptr(x_io)), ctypes.byref(info)))
+    d = info.as_dict()
+    d["S"] = S.value
+    return d
+
+
+def dwf_tune_set(ctx, prec, Ls, sites_per_block, s_per_thread, kernel_id=0):
+    _check(lib().dwf_tune_set(ctx.handle, int(kernel_id), int(prec), int(Ls), int(sites_per_block), int(s_per_thread)))
+
+
+def dwf_tune_get(ctx, prec, Ls, kernel_id=0):
+    a, b = _ci(0), _ci(0)
+    _check(lib().dwf_tune_get(ctx.handle, int(kernel_id), int(prec), int(Ls), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+from .fields import Lattice  # noqa: E402,F401

@@ -1,0 +1,192 @@
+// Context, geometry tables, workspace arena and fifth-dimension matrices.
+#include "runtime.hpp"
+
+namespace dwf {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+void* ws_get(dwf_ctx* ctx, const std::string& name, size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  auto it = ctx->ws.find(name);
+  if (it != ctx->ws.end() && it->second.second >= bytes) return it->second.first;
+  if (it != ctx->ws.end()) {
+    DWF_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    DWF_CHECK_HIP(hipFree(it->second.first));
+    ctx->ws.erase(it);
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{DWF_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed (" + name + ")"};
+  }
+  ctx->ws[name] = {p, bytes};
+  return p;
+}
+
+double read_scalar(dwf_ctx* ctx, const double* dscalars, int slot) {
+  DWF_CHECK_HIP(hipMemcpyAsync(ctx->h_scalars + slot, dscalars + slot, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+  DWF_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  return ctx->h_scalars[slot];
+}
+
+// 4D checkerboard tables.  Lexicographic index i = x + X(y + Y(z + Z t)), parity
+// (x+y+z+t) mod 2, x_cb = i / 2 (X even).  For output parity p and site x_cb:
+// nbr = x_cb of x +- mu (in the other parity), linksrc = code of the link the hop
+// uses in that direction: 2 (mu V + i) + (1 if the hop crosses the antiperiodic T boundary).
+const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
+  for (auto& g : ctx->geoms)
+    if (g->dims[0] == dims[0] && g->dims[1] == dims[1] && g->dims[2] == dims[2] && g->dims[3] == dims[3] &&
+        g->tbc == tbc)
+      return g.get();
+  auto g = std::make_unique<Geometry>();
+  for (int k = 0; k < 4; ++k) g->dims[k] = dims[k];
+  g->tbc = tbc;
+  const int X = dims[0], Y = dims[1], Z = dims[2], T = dims[3];
+  g->V = long(X) * Y * Z * T;
+  g->nsites = g->V / 2;
+  if (4 * g->V * 2 >= (1L << 31)) throw Error{DWF_ERR_ARG, "lattice too large for 32-bit link codes"};
+  const long ns = g->nsites;
+  std::vector<int> site(ns), nbr(ns * 8), lsrc(ns * 8);
+  auto idx = [&](int x, int y, int z, int t) { return long(x) + X * (long(y) + Y * (long(z) + long(Z) * t)); };
+  for (int p = 0; p < 2; ++p) {
+    for (long xc = 0; xc < ns; ++xc) {
+      const long i0 = 2 * xc;
+      const int xh = int(i0 % X);
+      long rest = i0 / X;
+      const int y = int(rest % Y);
+      rest /= Y;
+      const int z = int(rest % Z);
+      const int t = int(rest / Z);
+      const int x = xh + ((y + z + t + p) & 1);
+      const long i = idx(x, y, z, t);
+      site[xc] = int(i);
+      const int c[4] = {x, y, z, t};
+      for (int mu = 0; mu < 4; ++mu) {
+        int f[4] = {c[0], c[1], c[2], c[3]}, bk[4] = {c[0], c[1], c[2], c[3]};
+        f[mu] = (c[mu] + 1) % dims[mu];
+        bk[mu] = (c[mu] - 1 + dims[mu]) % dims[mu];
+        const long jf = idx(f[0], f[1], f[2], f[3]);
+        const long jb = idx(bk[0], bk[1], bk[2], bk[3]);
+        nbr[xc * 8 + mu] = int(jf / 2);
+        nbr[xc * 8 + 4 + mu] = int(jb / 2);
+        const int phf = (tbc && mu == 3 && c[3] == T - 1) ? 1 : 0;
+        const int phb = (tbc && mu == 3 && c[3] == 0) ? 1 : 0;
+        lsrc[xc * 8 + mu] = int(2 * (long(mu) * g->V + i) + phf);
+        lsrc[xc * 8 + 4 + mu] = int(2 * (long(mu) * g->V + jb) + phb);
+      }
+    }
+    DWF_CHECK_HIP(hipMalloc(&g->d_site[p], ns * sizeof(int)));
+    DWF_CHECK_HIP(hipMalloc(&g->d_nbr[p], ns * 8 * sizeof(int)));
+    DWF_CHECK_HIP(hipMalloc(&g->d_linksrc[p], ns * 8 * sizeof(int)));
+    DWF_CHECK_HIP(hipMemcpy(g->d_site[p], site.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+    DWF_CHECK_HIP(hipMemcpy(g->d_nbr[p], nbr.data(), ns * 8 * sizeof(int), hipMemcpyHostToDevice));
+    DWF_CHECK_HIP(hipMemcpy(g->d_linksrc[p], lsrc.data(), ns * 8 * sizeof(int), hipMemcpyHostToDevice));
+  }
+  ctx->geoms.push_back(std::move(g));
+  return ctx->geoms.back().get();
+}
+
+LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls) {
+  auto it = ctx->tune.find((long long)prec * 100000 + Ls);
+  if (it != ctx->tune.end()) return it->second;
+  LaunchCfg c;
+  c.ns = 1;
+  c.xcd = 1;
+  int spb = 256 / Ls;
+  if (spb < 1) spb = 1;
+  while (spb > 1 && (spb * Ls) % 64 != 0) --spb;
+  if ((spb * Ls) % 64 != 0) spb = 256 / Ls > 0 ? 256 / Ls : 1;
+  c.spb = spb;
+  return c;
+}
+
+// Per-chirality Ls x Ls matrices of the site-local fifth-dimension operators.
+// Chirality 0 (spins 0,1; P+) sees S~ as S- (psi_{s-1}, psi_{-1} = -m psi_{Ls-1});
+// chirality 1 (spins 2,3; P-) sees S+ (psi_{s+1}, psi_{Ls} = -m psi_0).
+// A = alpha + beta S with alpha = b d + 1, beta = c d - 1, d = 4 - M5; F = b + c S.
+// A^-1 by the closed form (alpha + beta S)^-1 = sum_{k<Ls} (-z)^k S^k / (alpha (1 + m (-z)^Ls)),
+// z = beta / alpha, which follows from S^Ls = -m.
+static std::vector<double> shift_matrix(int Ls, double m, int ch) {
+  std::vector<double> S(size_t(Ls) * Ls, 0.0);
+  for (int s = 0; s < Ls; ++s) {
+    if (ch == 0) {
+      if (s >= 1) S[s * Ls + s - 1] = 1.0; else S[s * Ls + Ls - 1] = -m;
+    } else {
+      if (s + 1 < Ls) S[s * Ls + s + 1] = 1.0; else S[s * Ls + 0] = -m;
+    }
+  }
+  return S;
+}
+
+static std::vector<double> matmul(const std::vector<double>& A, const std::vector<double>& B, int n) {
+  std::vector<double> C(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double a = A[i * n + k];
+      if (a == 0.0) continue;
+      for (int j = 0; j < n; ++j) C[i * n + j] += a * B[k * n + j];
+    }
+  return C;
+}
+
+static std::vector<double> transpose(const std::vector<double>& A, int n) {
+  std::vector<double> T(size_t(n) * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T[j * n + i] = A[i * n + j];
+  return T;
+}
+
+const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec) {
+  char key[256];
+  snprintf(key, sizeof(key), "%d|%.17g|%.17g|%.17g|%.17g|%d", Ls, M5, m, b, c, prec == 0 ? 0 : 1);
+  auto it = ctx->emats.find(key);
+  if (it != ctx->emats.end()) return it->second.first;
+  const int n = Ls;
+  const double d = 4.0 - M5, alpha = b * d + 1.0, beta = c * d - 1.0;
+  if (std::fabs(alpha) < 1e-14) throw Error{DWF_ERR_ARG, "b (4 - M5) + 1 = 0: A is not invertible by the closed form"};
+  const double z = beta / alpha;
+  const double denom = alpha * (1.0 + m * std::pow(-z, Ls));
+  if (std::fabs(denom) < 1e-300) throw Error{DWF_ERR_ARG, "singular fifth-dimension block A"};
+  std::vector<double> table(size_t(E_COUNT) * 2 * n * n, 0.0);
+  for (int ch = 0; ch < 2; ++ch) {
+    const std::vector<double> S = shift_matrix(Ls, m, ch);
+    std::vector<double> I(size_t(n) * n, 0.0);
+    for (int s = 0; s < n; ++s) I[s * n + s] = 1.0;
+    std::vector<double> A(size_t(n) * n), F(size_t(n) * n), Ainv(size_t(n) * n, 0.0), Sk = I;
+    for (int k = 0; k < n * n; ++k) {
+      A[k] = alpha * I[k] + beta * S[k];
+      F[k] = b * I[k] + c * S[k];
+    }
+    double coef = 1.0 / denom;
+    for (int k = 0; k < Ls; ++k) {
+      for (int q = 0; q < n * n; ++q) Ainv[q] += coef * Sk[q];
+      Sk = matmul(Sk, S, n);
+      coef *= -z;
+    }
+    const std::vector<double> Adag = transpose(A, n), Ainvdag = transpose(Ainv, n), Fdag = transpose(F, n);
+    const std::vector<double> AinvdagFdag = matmul(Ainvdag, Fdag, n);
+    const std::vector<double>* mats[E_COUNT] = {&A, &Adag, &Ainv, &Ainvdag, &F, &Fdag, &AinvdagFdag};
+    for (int e = 0; e < E_COUNT; ++e)
+      std::memcpy(&table[(size_t(e) * 2 + ch) * n * n], mats[e]->data(), sizeof(double) * n * n);
+  }
+  void* dptr = nullptr;
+  size_t bytes;
+  if (prec == 0) {
+    bytes = table.size() * sizeof(double);
+    DWF_CHECK_HIP(hipMalloc(&dptr, bytes));
+    DWF_CHECK_HIP(hipMemcpy(dptr, table.data(), bytes, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> tf(table.begin(), table.end());
+    bytes = tf.size() * sizeof(float);
+    DWF_CHECK_HIP(hipMalloc(&dptr, bytes));
+    DWF_CHECK_HIP(hipMemcpy(dptr, tf.data(), bytes, hipMemcpyHostToDevice));
+  }
+  ctx->emats[key] = {dptr, bytes};
+  return dptr;
+}
+
+}  // namespace dwf

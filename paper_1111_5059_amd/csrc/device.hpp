@@ -1,0 +1,260 @@
+// Device-side building blocks for gfx950: storage precisions, complex
+// arithmetic, and the chiral-basis spin projectors (1 -+ gamma_mu).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace dwf {
+
+// ----------------------------------------------------------------- complex
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmake(R a, R b) { return {a, b}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// i * a
+template <typename R>
+__device__ __forceinline__ cx<R> ci(cx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cfma(cx<R> a, cx<R> b, cx<R> acc) {  // acc + a*b
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+
+// ----------------------------------------------------------------- bf16 (round to nearest even)
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// ----------------------------------------------------------------- storage precisions
+// Each precision stores one complex number as a pair (re, im) of its storage
+// type; arithmetic is FP64 for FP64 and FP32 for everything else.  FP16 spinors
+// carry a per-(site, s) FP32 norm (max |component| of the 5D site).
+struct P64 {
+  using S = double2;
+  using R = double;
+  static constexpr bool NORM = false;
+  static constexpr int ID = 0;
+  __device__ __forceinline__ static cx<R> ld(const S& v) { return {v.x, v.y}; }
+  __device__ __forceinline__ static S st(cx<R> a) { return make_double2(a.re, a.im); }
+};
+struct P32 {
+  using S = float2;
+  using R = float;
+  static constexpr bool NORM = false;
+  static constexpr int ID = 1;
+  __device__ __forceinline__ static cx<R> ld(const S& v) { return {v.x, v.y}; }
+  __device__ __forceinline__ static S st(cx<R> a) { return make_float2(a.re, a.im); }
+};
+struct P16 {
+  using S = __half2;
+  using R = float;
+  static constexpr bool NORM = true;
+  static constexpr int ID = 2;
+  __device__ __forceinline__ static cx<R> ld(const S& v) {
+    float2 f = __half22float2(v);
+    return {f.x, f.y};
+  }
+  __device__ __forceinline__ static S st(cx<R> a) { return __floats2half2_rn(a.re, a.im); }
+};
+struct PB16 {
+  using S = uint32_t;
+  using R = float;
+  static constexpr bool NORM = false;
+  static constexpr int ID = 3;
+  __device__ __forceinline__ static cx<R> ld(const S& v) {
+    return {bf16_to_f32(uint16_t(v & 0xffffu)), bf16_to_f32(uint16_t(v >> 16))};
+  }
+  __device__ __forceinline__ static S st(cx<R> a) {
+    return uint32_t(f32_to_bf16(a.re)) | (uint32_t(f32_to_bf16(a.im)) << 16);
+  }
+};
+
+// A half field of one parity: data[(x_cb*12 + k)*Ls + s], norm[x_cb*Ls + s] (FP16 only)
+template <typename P>
+struct Half {
+  typename P::S* data;
+  float* norm;
+};
+template <typename P>
+struct CHalf {
+  const typename P::S* data;
+  const float* norm;
+};
+
+// bytes of one half field (nsites 4D checkerboard sites, Ls slices)
+template <typename P>
+__host__ __device__ inline size_t half_bytes(long nsites, int Ls) {
+  size_t b = size_t(nsites) * 12 * Ls * sizeof(typename P::S);
+  if (P::NORM) b += size_t(nsites) * Ls * sizeof(float);
+  b = (b + 255) & ~size_t(255);
+  return b;
+}
+
+template <typename P>
+__host__ __device__ inline Half<P> half_view(void* base, long nsites, int Ls) {
+  Half<P> h;
+  h.data = reinterpret_cast<typename P::S*>(base);
+  h.norm = P::NORM ? reinterpret_cast<float*>(reinterpret_cast<char*>(base) +
+                                              size_t(nsites) * 12 * Ls * sizeof(typename P::S))
+                   : nullptr;
+  return h;
+}
+template <typename P>
+__host__ __device__ inline CHalf<P> chalf_view(const void* base, long nsites, int Ls) {
+  Half<P> h = half_view<P>(const_cast<void*>(base), nsites, Ls);
+  return {h.data, h.norm};
+}
+
+// Load the 12 complex components of 5D site (x, s)
+template <typename P>
+__device__ __forceinline__ void load_spinor(CHalf<P> f, long x, int s, int Ls, cx<typename P::R> v[12]) {
+  using R = typename P::R;
+  const typename P::S* p = f.data + size_t(x) * 12 * Ls + s;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = P::ld(p[k * Ls]);
+  if constexpr (P::NORM) {
+    const R n = f.norm[size_t(x) * Ls + s];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = n * v[k];
+  }
+}
+
+// Load spin components [k0, k0+6) of 5D site (x, s)
+template <typename P>
+__device__ __forceinline__ void load_half_spinor(CHalf<P> f, long x, int s, int Ls, int k0, cx<typename P::R> v[6]) {
+  using R = typename P::R;
+  const typename P::S* p = f.data + (size_t(x) * 12 + k0) * Ls + s;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = P::ld(p[k * Ls]);
+  if constexpr (P::NORM) {
+    const R n = f.norm[size_t(x) * Ls + s];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = n * v[k];
+  }
+}
+
+template <typename P>
+__device__ __forceinline__ void store_spinor(Half<P> f, long x, int s, int Ls, const cx<typename P::R> v[12]) {
+  using R = typename P::R;
+  typename P::S* p = f.data + size_t(x) * 12 * Ls + s;
+  if constexpr (P::NORM) {
+    R m = R(0);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+    const R n = m > R(0) ? m : R(1);
+    const R inv = R(1) / n;
+    f.norm[size_t(x) * Ls + s] = n;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k * Ls] = P::st(inv * v[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k * Ls] = P::st(v[k]);
+  }
+}
+
+// ----------------------------------------------------------------- spin projection
+// Chiral basis: g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0, 1], [1, 0]].
+// For the projector (1 + sg g_mu), sg = +-1, the two independent rows are
+//   h0 = psi0 + a0 psi_j0,  h1 = psi1 + a1 psi_j1
+// and rows 2, 3 are multiples of h0/h1.  (Derived from the matrices above.)
+//   mu=x: h0 = psi0 - sg i psi3, h1 = psi1 - sg i psi2; r2 = sg i h1, r3 = sg i h0
+//   mu=y: h0 = psi0 - sg psi3,   h1 = psi1 + sg psi2;   r2 = sg h1,   r3 = -sg h0
+//   mu=z: h0 = psi0 - sg i psi2, h1 = psi1 + sg i psi3; r2 = sg i h0, r3 = -sg i h1
+//   mu=t: h0 = psi0 + sg psi2,   h1 = psi1 + sg psi3;   r2 = sg h0,   r3 = sg h1
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void project(const cx<R> psi[12], cx<R> h[6]) {
+  const R sg = R(SG);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<R> p0 = psi[0 * 3 + c], p1 = psi[1 * 3 + c], p2 = psi[2 * 3 + c], p3 = psi[3 * 3 + c];
+    if constexpr (MU == 0) {
+      h[c] = p0 - sg * ci(p3);
+      h[3 + c] = p1 - sg * ci(p2);
+    } else if constexpr (MU == 1) {
+      h[c] = p0 - sg * p3;
+      h[3 + c] = p1 + sg * p2;
+    } else if constexpr (MU == 2) {
+      h[c] = p0 - sg * ci(p2);
+      h[3 + c] = p1 + sg * ci(p3);
+    } else {
+      h[c] = p0 + sg * p2;
+      h[3 + c] = p1 + sg * p3;
+    }
+  }
+}
+
+// acc += (1 + sg g_mu)-reconstruction of the projected, link-multiplied half spinor u
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void reconstruct_acc(const cx<R> u[6], cx<R> acc[12]) {
+  const R sg = R(SG);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<R> u0 = u[c], u1 = u[3 + c];
+    acc[0 * 3 + c] = acc[0 * 3 + c] + u0;
+    acc[1 * 3 + c] = acc[1 * 3 + c] + u1;
+    if constexpr (MU == 0) {
+      acc[2 * 3 + c] = acc[2 * 3 + c] + sg * ci(u1);
+      acc[3 * 3 + c] = acc[3 * 3 + c] + sg * ci(u0);
+    } else if constexpr (MU == 1) {
+      acc[2 * 3 + c] = acc[2 * 3 + c] + sg * u1;
+      acc[3 * 3 + c] = acc[3 * 3 + c] - sg * u0;
+    } else if constexpr (MU == 2) {
+      acc[2 * 3 + c] = acc[2 * 3 + c] + sg * ci(u0);
+      acc[3 * 3 + c] = acc[3 * 3 + c] - sg * ci(u1);
+    } else {
+      acc[2 * 3 + c] = acc[2 * 3 + c] + sg * u0;
+      acc[3 * 3 + c] = acc[3 * 3 + c] + sg * u1;
+    }
+  }
+}
+
+// u = M h for both half-spinor rows (M: 3x3 complex, row-major)
+template <typename R>
+__device__ __forceinline__ void su3_mul_half(const cx<R> M[9], const cx<R> h[6], cx<R> u[6]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> s = cmul(M[a * 3 + 0], h[r * 3 + 0]);
+      s = cfma(M[a * 3 + 1], h[r * 3 + 1], s);
+      s = cfma(M[a * 3 + 2], h[r * 3 + 2], s);
+      u[r * 3 + a] = s;
+    }
+}
+
+// XCD-aware block order: the hardware deals workgroups round-robin over the 8
+// XCDs; remap so that each XCD walks one contiguous range of the lattice and
+// neighbouring sites share its L2.
+__device__ __forceinline__ long xcd_block(long bid, long nblocks) {
+  const long q = nblocks >> 3, r = nblocks & 7;
+  const long xcd = bid & 7, idx = bid >> 3;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+}  // namespace dwf

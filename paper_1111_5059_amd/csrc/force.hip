@@ -1,0 +1,250 @@
+// Fermion force (Sec. 2: e_a(S) with e_a(U) = T_a U) as the adjoint of the hop:
+// for S = phi^+ (M^+ M)^-1 phi, X = (M^+M)^-1 phi, the derivative along a link
+// reduces to   dS = -Re <Z, dH W>   with W = F (X + X_e), Z = Y_o' + Y_e'
+// (X_e = A^-1 B_eo X, Y_o' = A^-dag M X, Y_e' = A^-dag B_oe^dag Y_o', F = b + c S~).
+// For the link U_mu(x) only two hop terms contribute:
+//   <Z, dH W> = tr(dU Q1) + tr(dU^+ Q2),
+//   Q1 = sum_{s,spin} [(1 - g_mu) W(x+mu)] Z(x)^+,  Q2 = sum_{s,spin} [(1 + g_mu) W(x)] Z(x+mu)^+ .
+// One thread per link accumulates Q1, Q2 over s (FP64), then writes either
+//   F = sum_a e_a T_a = -1/2 TA(Q2 U^+ - U Q1)     (T_a = i lambda_a / 2)
+// or the ambient gradient G = -(Q1^+ + Q2) (dS = Re sum conj(G) dU).
+// The force-gradient update U' = exp(-eps F) U uses the Cayley-Hamilton form of
+// the SU(3) exponential of Morningstar and Peardon (Phys. Rev. D 69, 054501, 2004).
+#include "kernels.hpp"
+
+namespace dwf {
+
+using C = cx<double>;
+
+__device__ __forceinline__ C cconj(C a) { return {a.re, -a.im}; }
+
+template <int MU, int SG>
+__device__ __forceinline__ void spin_project_full(const C w[12], C pw[12]) {
+  C h[6];
+  project<MU, SG>(w, h);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) pw[k] = {0.0, 0.0};
+  reconstruct_acc<MU, SG>(h, pw);
+}
+
+template <int MU, int SG>
+__device__ __forceinline__ void outer_acc(const C w[12], const C z[12], C Q[9]) {
+  C pw[12];
+  spin_project_full<MU, SG>(w, pw);
+#pragma unroll
+  for (int be = 0; be < 4; ++be)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Q[r * 3 + c] = cfma(pw[be * 3 + r], cconj(z[be * 3 + c]), Q[r * 3 + c]);
+}
+
+struct ForceArgs {
+  CHalf<P64> W[2], Z[2];
+  const int* nbr[2];
+  const int* linksrc[2];
+  const double2* U;
+  long nsites;
+  int Ls;
+  int kind;
+  double2* F;
+};
+
+template <int MU>
+__device__ void force_link(const ForceArgs& a, int p, long x) {
+  const long xf = a.nbr[p][x * 8 + MU];
+  C Q1[9], Q2[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Q1[k] = Q2[k] = {0.0, 0.0};
+  for (int s = 0; s < a.Ls; ++s) {
+    C w[12], z[12];
+    load_spinor<P64>(a.W[1 - p], xf, s, a.Ls, w);
+    load_spinor<P64>(a.Z[p], x, s, a.Ls, z);
+    outer_acc<MU, -1>(w, z, Q1);
+    load_spinor<P64>(a.W[p], x, s, a.Ls, w);
+    load_spinor<P64>(a.Z[1 - p], xf, s, a.Ls, z);
+    outer_acc<MU, +1>(w, z, Q2);
+  }
+  const int code = a.linksrc[p][x * 8 + MU];
+  const long l = code >> 1;
+  const double ph = (code & 1) ? -1.0 : 1.0;
+  C U[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) U[k] = {ph * a.U[l * 9 + k].x, ph * a.U[l * 9 + k].y};
+  C out[9];
+  if (a.kind == 0) {
+    // M = Q2 U^+ - U Q1 ; F = -1/2 [ (M - M^+)/2 - tr(M - M^+)/6 ]
+    C M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C m = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          m = cfma(Q2[r * 3 + k], cconj(U[c * 3 + k]), m);
+          m = m - cmul(U[r * 3 + k], Q1[k * 3 + c]);
+        }
+        M[r * 3 + c] = m;
+      }
+    const double trim = (M[0].im + M[4].im + M[8].im);  // tr(M - M^+) = 2 i Im tr M
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C a1 = M[r * 3 + c], a2 = cconj(M[c * 3 + r]);
+        C ta = {0.5 * (a1.re - a2.re), 0.5 * (a1.im - a2.im)};
+        if (r == c) ta.im -= trim / 3.0;
+        out[r * 3 + c] = {-0.5 * ta.re, -0.5 * ta.im};
+      }
+  } else {
+    // G = -ph (Q1^+ + Q2)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C g = cconj(Q1[c * 3 + r]) + Q2[r * 3 + c];
+        out[r * 3 + c] = {-ph * g.re, -ph * g.im};
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) a.F[l * 9 + k] = make_double2(out[k].re, out[k].im);
+}
+
+__global__ void __launch_bounds__(256) force_kernel(ForceArgs a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * a.nsites * 4) return;
+  const int mu = int(i & 3);
+  const long j = i >> 2;
+  const int p = j >= a.nsites ? 1 : 0;
+  const long x = j - p * a.nsites;
+  switch (mu) {
+    case 0: force_link<0>(a, p, x); break;
+    case 1: force_link<1>(a, p, x); break;
+    case 2: force_link<2>(a, p, x); break;
+    default: force_link<3>(a, p, x); break;
+  }
+}
+
+int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CHalf<P64> Z_e, CHalf<P64> Z_o,
+                 const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st) {
+  (void)tbc;
+  (void)dims;
+  ForceArgs a;
+  a.W[0] = W_e; a.W[1] = W_o;
+  a.Z[0] = Z_e; a.Z[1] = Z_o;
+  a.nbr[0] = g.nbr[0]; a.nbr[1] = g.nbr[1];
+  a.linksrc[0] = g.linksrc[0]; a.linksrc[1] = g.linksrc[1];
+  a.U = U_natural;
+  a.nsites = g.nsites;
+  a.Ls = Ls;
+  a.kind = kind;
+  a.F = F;
+  const long n = 2 * g.nsites * 4;
+  hipLaunchKernelGGL(force_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// ------------------------------------------------------------------ SU(3) exponential
+__device__ void mat3_mul(const C* A, const C* B, C* R) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C s = {0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = cfma(A[r * 3 + k], B[k * 3 + c], s);
+      R[r * 3 + c] = s;
+    }
+}
+
+// exp(i Q) for Hermitian traceless Q:  f0 + f1 Q + f2 Q^2  (Morningstar-Peardon)
+__device__ void expi_hermitian(const C Q[9], C E[9]) {
+  C Q2[9];
+  mat3_mul(Q, Q, Q2);
+  const double c1 = 0.5 * (Q2[0].re + Q2[4].re + Q2[8].re);
+  C f0, f1, f2;
+  if (c1 < 1e-12) {
+    // |Q| < 1e-6: series through Q^2 is exact to rounding for these terms; keep to third order
+    // exp(iQ) = 1 + iQ - Q^2/2 - i Q^3/6 ; with Q^3 = c1 Q + c0 (Cayley-Hamilton for traceless Q)
+    C Q3[9];
+    mat3_mul(Q2, Q, Q3);
+    const double c0 = (Q3[0].re + Q3[4].re + Q3[8].re) / 3.0;
+    f0 = {1.0, -c0 / 6.0};
+    f1 = {0.0, 1.0 - c1 / 6.0};
+    f2 = {-0.5, 0.0};
+  } else {
+    C Q3[9];
+    mat3_mul(Q2, Q, Q3);
+    double c0 = (Q3[0].re + Q3[4].re + Q3[8].re) / 3.0;  // det Q
+    const bool neg = c0 < 0.0;
+    if (neg) c0 = -c0;
+    const double c0max = 2.0 * pow(c1 / 3.0, 1.5);
+    double r = c0 / c0max;
+    if (r > 1.0) r = 1.0;
+    const double theta = acos(r);
+    const double u = sqrt(c1 / 3.0) * cos(theta / 3.0);
+    const double w = sqrt(c1) * sin(theta / 3.0);
+    const double u2 = u * u, w2 = w * w;
+    const double xi0 = fabs(w) < 0.05 ? 1.0 - w2 / 6.0 * (1.0 - w2 / 20.0 * (1.0 - w2 / 42.0)) : sin(w) / w;
+    const double cw = cos(w);
+    const C e2iu = {cos(2.0 * u), sin(2.0 * u)};
+    const C emiu = {cos(u), -sin(u)};
+    const C h0 = cmul(C{u2 - w2, 0.0}, e2iu) + cmul(emiu, C{8.0 * u2 * cw, 2.0 * u * (3.0 * u2 + w2) * xi0});
+    const C h1 = cmul(C{2.0 * u, 0.0}, e2iu) - cmul(emiu, C{2.0 * u * cw, -(3.0 * u2 - w2) * xi0});
+    const C h2 = e2iu - cmul(emiu, C{cw, 3.0 * u * xi0});
+    const double inv = 1.0 / (9.0 * u2 - w2);
+    f0 = inv * h0;
+    f1 = inv * h1;
+    f2 = inv * h2;
+    if (neg) {
+      f0 = cconj(f0);
+      f1 = {-f1.re, f1.im};
+      f2 = cconj(f2);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    C v = cmul(f1, Q[k]) + cmul(f2, Q2[k]);
+    if (k % 4 == 0) v = v + f0;
+    E[k] = v;
+  }
+}
+
+// U' = exp(-eps F) U, F anti-Hermitian traceless: -eps F = i Q with Q = i eps F Hermitian
+__global__ void __launch_bounds__(256) fg_update_kernel(const double2* F, const double2* U, double eps, double2* Uout,
+                                                         long nlinks) {
+  const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlinks) return;
+  C Q[9], E[9], Ul[9], R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 f = F[l * 9 + k];
+    Q[k] = {-eps * f.y, eps * f.x};  // i eps F
+    Ul[k] = {U[l * 9 + k].x, U[l * 9 + k].y};
+  }
+  // enforce exact hermiticity / tracelessness of Q against rounding in F
+  C Qh[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const C a = Q[r * 3 + c], b = cconj(Q[c * 3 + r]);
+      Qh[r * 3 + c] = {0.5 * (a.re + b.re), 0.5 * (a.im + b.im)};
+    }
+  const double tr = (Qh[0].re + Qh[4].re + Qh[8].re) / 3.0;
+  Qh[0].re -= tr; Qh[4].re -= tr; Qh[8].re -= tr;
+  expi_hermitian(Qh, E);
+  mat3_mul(E, Ul, R);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Uout[l * 9 + k] = make_double2(R[k].re, R[k].im);
+}
+
+int launch_fg_update(const double2* F, const double2* U, double eps, double2* Uout, long nlinks, hipStream_t st) {
+  if (nlinks <= 0) return 0;
+  hipLaunchKernelGGL(fg_update_kernel, dim3((unsigned)((nlinks + 255) / 256)), dim3(256), 0, st, F, U, eps, Uout,
+                     nlinks);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace dwf

@@ -1,0 +1,309 @@
+// Wilson hop (the 4D operator the paper counts as its unit of cost, Table 1)
+// over a 5D half field, and the site-local fifth-dimension kernel, for gfx950.
+//
+// Mapping: one thread owns one 4D checkerboard site and NS of its Ls slices
+// (s = s0, s0 + Ls/NS, ...); the Ls/NS threads of a site are consecutive, so
+// a wave reads contiguous runs of the s-fastest layout [x_cb][12][Ls] for
+// every neighbour, and all threads of a site read the same link addresses
+// (one request per wave).  Each of the 8 links is loaded once per thread and
+// reused for its NS slices.  Spinors are spin-projected to half spinors before
+// the SU(3) multiply (two 3x3 mat-vecs instead of four).
+//
+// Optional fused stages (Sec. 4 operators, even-odd form):
+//   prologue  F = b + c S~ applied to each neighbour spinor as it is read
+//             (Moebius input factor: needs the upper spins of s-1 and the lower
+//             spins of s+1 of the same neighbour, same cache lines);
+//   epilogue  per-chirality Ls x Ls matrix along s (A^-1, A^-dag F^dag, ...),
+//             through LDS: a workgroup holds all Ls slices of its sites;
+//   axpy      out = ax * x + result;  |out|^2 partials per workgroup.
+#pragma once
+#include "kernels.hpp"
+
+namespace dwf {
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  return s;
+}
+
+template <typename P, bool PRO>
+__device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, cx<typename P::R> psi[12]) {
+  using R = typename P::R;
+  load_spinor<P>(a.in, y, s, a.Ls, psi);
+  if constexpr (PRO) {
+    const int Ls = a.Ls;
+    cx<R> up[6], lo[6];
+    int su = s - 1, sl = s + 1;
+    R fu = a.pc, fl = a.pc;
+    if (su < 0) { su = Ls - 1; fu = -a.pc * a.pm; }
+    if (sl >= Ls) { sl = 0; fl = -a.pc * a.pm; }
+    load_half_spinor<P>(a.in, y, su, Ls, 0, up);  // P+ (spins 0,1) picks psi_{s-1}
+    load_half_spinor<P>(a.in, y, sl, Ls, 6, lo);  // P- (spins 2,3) picks psi_{s+1}
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      psi[k] = a.pb * psi[k] + fu * up[k];
+      psi[6 + k] = a.pb * psi[6 + k] + fl * lo[k];
+    }
+  }
+}
+
+// One of the 8 hop directions: D = 0..3 forward (x+mu), 4..7 backward (x-mu).
+// H uses (1 - g_mu) forward and (1 + g_mu) backward; H^dag the opposite.
+template <int D, bool DAG, bool PRO, int NS, typename P>
+__device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, const typename P::S* L, int s0, int tps,
+                                        cx<typename P::R> (&acc)[NS][12]) {
+  using R = typename P::R;
+  constexpr int MU = D & 3;
+  constexpr bool FWD = D < 4;
+  constexpr int SG = (FWD != DAG) ? -1 : +1;
+  const long y = nb[D];
+  cx<R> U[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) U[e] = P::ld(L[D * 9 + e]);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    cx<R> psi[12], h[6], u[6];
+    load_input<P, PRO>(a, y, s0 + j * tps, psi);
+    project<MU, SG>(psi, h);
+    su3_mul_half(U, h, u);
+    reconstruct_acc<MU, SG>(u, acc[j]);
+  }
+}
+
+template <typename P, int NS, bool DAG, bool PRO, bool EPI>
+__global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd) {
+  using R = typename P::R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int Ls = a.Ls, tps = Ls / NS;
+  const long bid = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+  const int lsite = threadIdx.x / tps;
+  const int s0 = threadIdx.x - lsite * tps;
+  const long x = bid * spb + lsite;
+  const bool active = (lsite < spb) && (x < a.nsites);
+  cx<R> acc[NS][12];
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[j][k] = {R(0), R(0)};
+  if (active) {
+    const int* nb = a.nbr + x * 8;
+    const typename P::S* L = a.links + x * 72;
+    hop_dir<0, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<1, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<2, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<3, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<4, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<5, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<6, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<7, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+  }
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
+  if constexpr (EPI) {
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) lds[(lsite * 12 + k) * Ls + s0 + j * tps] = acc[j][k];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const int s = s0 + j * tps;
+        const R* E0 = a.E + s * Ls;
+        const R* E1 = a.E + Ls * Ls + s * Ls;
+        cx<R> o[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[k] = {R(0), R(0)};
+        const cx<R>* row = lds + lsite * 12 * Ls;
+        for (int sp = 0; sp < Ls; ++sp) {
+          const R e0 = E0[sp], e1 = E1[sp];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const cx<R> v = row[k * Ls + sp];
+            o[k].re = fma(e0, v.re, o[k].re);
+            o[k].im = fma(e0, v.im, o[k].im);
+          }
+#pragma unroll
+          for (int k = 6; k < 12; ++k) {
+            const cx<R> v = row[k * Ls + sp];
+            o[k].re = fma(e1, v.re, o[k].re);
+            o[k].im = fma(e1, v.im, o[k].im);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[j][k] = o[k];
+      }
+    }
+  }
+  double nrm = 0.0;
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int s = s0 + j * tps;
+      if (a.x.data) {
+        cx<R> xv[12];
+        load_spinor<P>(a.x, x, s, Ls, xv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[j][k] = acc[j][k] + a.ax * xv[k];
+      }
+      if (a.norm_partials) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+          nrm += double(acc[j][k].re) * double(acc[j][k].re) + double(acc[j][k].im) * double(acc[j][k].im);
+      }
+      store_spinor<P>(a.out, x, s, Ls, acc[j]);
+    }
+  }
+  if (a.norm_partials) {
+    const double t = block_sum(nrm, red);
+    if (threadIdx.x == 0) a.norm_partials[blockIdx.x] = t;
+  }
+}
+
+template <typename P, int NS, bool DAG, bool PRO, bool EPI>
+static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
+  using R = typename P::R;
+  const int tps = a.Ls / NS;
+  const int threads = cfg.spb * tps;
+  const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
+  const size_t lds = EPI ? size_t(cfg.spb) * 12 * a.Ls * sizeof(cx<R>) : 0;
+  hipLaunchKernelGGL((hop_kernel<P, NS, DAG, PRO, EPI>), dim3((unsigned)blocks), dim3(threads), lds, st, a, cfg.spb,
+                     cfg.xcd);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename P, int NS>
+static int launch_hop_ns(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
+  const bool epi = a.E != nullptr;
+  if (dag) {
+    return epi ? launch_hop_t<P, NS, true, false, true>(a, cfg, st) : launch_hop_t<P, NS, true, false, false>(a, cfg, st);
+  }
+  if (pro) {
+    return epi ? launch_hop_t<P, NS, false, true, true>(a, cfg, st) : launch_hop_t<P, NS, false, true, false>(a, cfg, st);
+  }
+  return epi ? launch_hop_t<P, NS, false, false, true>(a, cfg, st) : launch_hop_t<P, NS, false, false, false>(a, cfg, st);
+}
+
+// Validates the launch shape against the kernel's assumptions before launching:
+// Ls divisible by NS, at most 256 threads per workgroup, LDS within 64 KiB.
+template <typename P>
+int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st) {
+  using R = typename P::R;
+  if (cfg.ns != 1 && cfg.ns != 2 && cfg.ns != 4) return -1;
+  if (a.Ls % cfg.ns != 0 || cfg.spb < 1) return -1;
+  if (dagger && prologue) return -1;
+  const int threads = cfg.spb * (a.Ls / cfg.ns);
+  if (threads > 256) return -1;
+  if (a.E && size_t(cfg.spb) * 12 * a.Ls * sizeof(cx<R>) > 65536) return -1;
+  if (a.nsites <= 0) return 0;
+  switch (cfg.ns) {
+    case 1: return launch_hop_ns<P, 1>(a, dagger, prologue, cfg, st);
+    case 2: return launch_hop_ns<P, 2>(a, dagger, prologue, cfg, st);
+    default: return launch_hop_ns<P, 4>(a, dagger, prologue, cfg, st);
+  }
+}
+
+// ------------------------------------------------------------------ site-local fifth-dimension matrices
+template <typename P>
+__global__ void __launch_bounds__(256) fifth_kernel(CHalf<P> in, Half<P> out, const typename P::R* E, CHalf<P> xin,
+                                                     typename P::R ax, long nsites, int Ls, int spb,
+                                                     double* norm_partials) {
+  using R = typename P::R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+  const int lsite = threadIdx.x / Ls;
+  const int s = threadIdx.x - lsite * Ls;
+  const long x = (long)blockIdx.x * spb + lsite;
+  const bool active = (lsite < spb) && (x < nsites);
+  if (active) {
+    cx<R> v[12];
+    load_spinor<P>(in, x, s, Ls, v);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) lds[(lsite * 12 + k) * Ls + s] = v[k];
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  if (active) {
+    cx<R> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) o[k] = {R(0), R(0)};
+    const R* E0 = E + s * Ls;
+    const R* E1 = E + Ls * Ls + s * Ls;
+    const cx<R>* row = lds + lsite * 12 * Ls;
+    for (int sp = 0; sp < Ls; ++sp) {
+      const R e0 = E0[sp], e1 = E1[sp];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        o[k].re = fma(e0, row[k * Ls + sp].re, o[k].re);
+        o[k].im = fma(e0, row[k * Ls + sp].im, o[k].im);
+      }
+#pragma unroll
+      for (int k = 6; k < 12; ++k) {
+        o[k].re = fma(e1, row[k * Ls + sp].re, o[k].re);
+        o[k].im = fma(e1, row[k * Ls + sp].im, o[k].im);
+      }
+    }
+    if (xin.data) {
+      cx<R> xv[12];
+      load_spinor<P>(xin, x, s, Ls, xv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) o[k] = o[k] + ax * xv[k];
+    }
+    if (norm_partials) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) nrm += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
+    }
+    store_spinor<P>(out, x, s, Ls, o);
+  }
+  if (norm_partials) {
+    const double t = block_sum(nrm, red);
+    if (threadIdx.x == 0) norm_partials[blockIdx.x] = t;
+  }
+}
+
+template <typename P>
+int launch_fifth(CHalf<P> in, Half<P> out, const typename P::R* E, CHalf<P> x, typename P::R ax, long nsites, int Ls,
+                 double* norm_partials, hipStream_t st) {
+  using R = typename P::R;
+  if (Ls < 1 || Ls > 256) return -1;
+  int spb = 256 / Ls;
+  if (spb < 1) spb = 1;
+  while (spb > 1 && size_t(spb) * 12 * Ls * sizeof(cx<R>) > 65536) --spb;
+  if (nsites <= 0) return 0;
+  const long blocks = (nsites + spb - 1) / spb;
+  const size_t lds = size_t(spb) * 12 * Ls * sizeof(cx<R>);
+  hipLaunchKernelGGL((fifth_kernel<P>), dim3((unsigned)blocks), dim3(spb * Ls), lds, st, in, out, E, x, ax, nsites, Ls,
+                     spb, norm_partials);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// number of workgroups launch_fifth / launch_hop use (partials array sizing)
+inline long fifth_blocks(long nsites, int Ls, size_t elem) {
+  int spb = 256 / Ls;
+  if (spb < 1) spb = 1;
+  while (spb > 1 && size_t(spb) * 12 * Ls * elem > 65536) --spb;
+  return (nsites + spb - 1) / spb;
+}
+
+}  // namespace dwf
+
+#define DWF_INSTANTIATE_HOP(P)                                                                                   \
+  template int dwf::launch_hop<P>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);                \
+  template int dwf::launch_fifth<P>(CHalf<P>, Half<P>, const P::R*, CHalf<P>, P::R, long, int, double*,         \
+                                    hipStream_t);

@@ -1,0 +1,109 @@
+// Host-side launch interface of the gfx950 kernels (no torch types).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "device.hpp"
+
+namespace dwf {
+
+// Arguments of one Wilson-hop launch over a half field (output parity fixed by
+// the link block and neighbour table handed in).
+//   out = ax * x + E . (scale * H F in)       (H^dag when dagger)
+// F = pb + pc S~ (prologue, optional), E = per-chirality Ls x Ls matrices
+// (epilogue, optional), x (axpy, optional).  norm_partials (optional) receives
+// one FP64 partial sum of |out|^2 per block.
+template <typename P>
+struct HopArgs {
+  CHalf<P> in;
+  Half<P> out;
+  const typename P::S* links;  // [nsites][8][9] for the output parity
+  const int* nbr;              // [nsites][8] neighbour x_cb in the input half
+  long nsites;
+  int Ls;
+  typename P::R scale;
+  typename P::R pb, pc, pm;    // prologue F = pb + pc S~, boundary factor -pm
+  const typename P::R* E;      // epilogue [2][Ls][Ls] or nullptr
+  CHalf<P> x;                  // axpy operand (data == nullptr: none)
+  typename P::R ax;
+  double* norm_partials;       // per-block sum |out|^2 or nullptr
+};
+
+struct LaunchCfg {
+  int spb;  // 4D sites per block
+  int ns;   // s-values per thread
+  int xcd;  // XCD-aware block order
+};
+
+template <typename P>
+int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st);
+
+// out = ax * x + E . in  (site-local fifth-dimension matrices), optional |out|^2 partials
+template <typename P>
+int launch_fifth(CHalf<P> in, Half<P> out, const typename P::R* E, CHalf<P> x, typename P::R ax, long nsites,
+                 int Ls, double* norm_partials, hipStream_t st);
+
+// ---------------------------------------------------------------- BLAS-1 / reductions
+// Every reduction writes per-block FP64 partials; reduce_partials sums them in
+// a fixed order (deterministic) into dst.
+int reduction_blocks(long n5);  // number of partial sums the BLAS reductions produce for n5 5D sites
+template <typename P>
+int launch_norm2(CHalf<P> a, long n5, int Ls, double* partials, hipStream_t st);
+template <typename P>
+int launch_dot(CHalf<P> a, CHalf<P> b, long n5, int Ls, double* partials /* 2 per block */, hipStream_t st);
+// y = a*x + b*y   (a, b real, host scalars)
+template <typename P>
+int launch_axpby(double a, CHalf<P> x, double b, Half<P> y, long n5, int Ls, hipStream_t st);
+// precision conversion of a half field
+template <typename Pi, typename Po>
+int launch_convert(CHalf<Pi> in, Half<Po> out, long n5, int Ls, hipStream_t st);
+// scalar slots on the device (CG scalars)
+enum ScalarSlot { S_RR = 0, S_RRNEW, S_QQ, S_ALPHA, S_BETA, S_TMP0, S_TMP1, S_TMP2, S_COUNT = 16 };
+// dst[slot] = sum(partials[0..n)) and the CG scalar update selected by mode:
+//   0: just store;  1: alpha = rr/qq (slot = S_QQ);  2: beta = rrnew/rr, rr = rrnew (slot = S_RRNEW)
+int launch_reduce(const double* partials, int n, int ncomp, double* scalars, int slot, int mode, hipStream_t st);
+// x += alpha p  (x in Px, p in P);  r -= alpha Ap;  partials of |r|^2
+template <typename P, typename Px>
+int launch_cg_update(Half<Px> x, CHalf<P> p, Half<P> r, CHalf<P> Ap, const double* scalars, long n5, int Ls,
+                     double* partials, hipStream_t st);
+// p = r + beta p  (and scalars[S_RR] = rr_new)
+template <typename P>
+int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, double rr_new, long n5, int Ls,
+                      hipStream_t st);
+// P / P^-1 of the domain-wall <-> overlap transformation on an FP64 half field
+int launch_pshift(CHalf<P64> in, Half<P64> out, int inverse, long nsites, int Ls, hipStream_t st);
+// out(s_out) = scale * in(s_in) on FP64 half fields of extents Ls_in, Ls_out
+int launch_slice_copy(CHalf<P64> in, int Ls_in, int s_in, Half<P64> out, int Ls_out, int s_out, double scale,
+                      long nsites, hipStream_t st);
+// x_hi += x_lo (then x_lo = 0)
+template <typename Px>
+int launch_accumulate(Half<P64> hi, Half<Px> lo, long n5, int Ls, hipStream_t st);
+int launch_zero(void* p, size_t bytes, hipStream_t st);
+int launch_set_scalar(double* scalars, int slot, double v, hipStream_t st);
+
+// ---------------------------------------------------------------- packing
+struct GeomTables {
+  const int* site[2];    // [nsites] lexicographic index of x_cb, per parity
+  const int* nbr[2];     // [nsites][8] neighbour x_cb (other parity) for output parity p
+  const int* linksrc[2]; // [nsites][8] (mu*V + i) of the link used, sign bit = boundary phase -1
+  long V, nsites;
+};
+template <typename P>
+int launch_pack_gauge(const GeomTables& g, const double2* natural, typename P::S* packed, hipStream_t st);
+template <typename P>
+int launch_pack_half(const GeomTables& g, int parity, int Ls, const double2* natural, Half<P> out,
+                     hipStream_t st);
+template <typename P>
+int launch_unpack_half(const GeomTables& g, int parity, int Ls, CHalf<P> in, double2* natural, hipStream_t st);
+template <typename Pi, typename Po>
+int launch_convert_links(const typename Pi::S* in, typename Po::S* out, long n, hipStream_t st);
+
+// ---------------------------------------------------------------- force
+// Per link (x, mu) of parity p sites x:  Q = sum_{s,spin} outer products (see force.hip)
+// writes either F = -1/2 TA(M) (kind 0) or the ambient gradient G (kind 1) to the
+// natural force layout.
+int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CHalf<P64> Z_e, CHalf<P64> Z_o,
+                 const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st);
+// U' = exp(-eps F) U per link (Cayley-Hamilton exponential), natural layouts
+int launch_fg_update(const double2* F, const double2* U, double eps, double2* Uout, long nlinks, hipStream_t st);
+
+}  // namespace dwf

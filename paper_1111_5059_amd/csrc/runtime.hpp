@@ -1,0 +1,193 @@
+// Host runtime: context, geometry tables, workspace arena and the even-odd
+// operator composition on top of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+#include <cmath>
+#include <cstring>
+#include "kernels.hpp"
+#include "../../include/dwf.h"
+
+namespace dwf {
+
+// error carried to the C boundary
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(const std::string& msg);
+
+#define DWF_CHECK_HIP(expr)                                                                 \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) throw ::dwf::Error{DWF_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)}; \
+  } while (0)
+#define DWF_CHECK_LAUNCH(expr)                                                              \
+  do {                                                                                      \
+    int rc_ = (expr);                                                                       \
+    if (rc_ == -1) throw ::dwf::Error{DWF_ERR_ARG, std::string("launch shape rejected: ") + #expr}; \
+    if (rc_ != 0) throw ::dwf::Error{DWF_ERR_HIP, std::string("kernel launch failed: ") + #expr + ": " + \
+                                     hipGetErrorString(hipGetLastError())};                 \
+  } while (0)
+
+// ------------------------------------------------------------------ geometry
+struct Geometry {
+  int dims[4];
+  int tbc;
+  long V, nsites;
+  int* d_site[2] = {nullptr, nullptr};
+  int* d_nbr[2] = {nullptr, nullptr};
+  int* d_linksrc[2] = {nullptr, nullptr};
+  GeomTables tables() const {
+    GeomTables t;
+    for (int p = 0; p < 2; ++p) {
+      t.site[p] = d_site[p];
+      t.nbr[p] = d_nbr[p];
+      t.linksrc[p] = d_linksrc[p];
+    }
+    t.V = V;
+    t.nsites = nsites;
+    return t;
+  }
+  ~Geometry() {
+    for (int p = 0; p < 2; ++p) {
+      if (d_site[p]) (void)hipFree(d_site[p]);
+      if (d_nbr[p]) (void)hipFree(d_nbr[p]);
+      if (d_linksrc[p]) (void)hipFree(d_linksrc[p]);
+    }
+  }
+};
+
+}  // namespace dwf
+
+struct dwf_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::map<std::string, std::pair<void*, size_t>> ws;
+  std::vector<std::unique_ptr<dwf::Geometry>> geoms;
+  std::map<std::string, std::pair<void*, size_t>> emats;  // fifth-dimension matrices by key
+  std::map<long long, dwf::LaunchCfg> tune;              // (prec, Ls) -> hop launch configuration
+  double* h_scalars = nullptr;                           // pinned host mirror of the CG scalars
+};
+
+namespace dwf {
+
+void* ws_get(dwf_ctx* ctx, const std::string& name, size_t bytes);
+const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc);
+LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls);
+// device buffer of the fifth-dimension matrices for one parameter set
+const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec);
+double read_scalar(dwf_ctx* ctx, const double* dscalars, int slot);
+
+// slots of the per-parameter fifth-dimension matrix table ([slot][2][Ls][Ls])
+enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_COUNT };
+
+template <typename P>
+size_t half_size(const Geometry* g, int Ls) { return half_bytes<P>(g->nsites, Ls); }
+
+template <typename P>
+Half<P> hview(void* base, const Geometry* g, int Ls) { return half_view<P>(base, g->nsites, Ls); }
+template <typename P>
+CHalf<P> chview(const void* base, const Geometry* g, int Ls) { return chalf_view<P>(base, g->nsites, Ls); }
+template <typename P>
+CHalf<P> cv(Half<P> h) { return {h.data, h.norm}; }
+template <typename P>
+CHalf<P> none() { return {nullptr, nullptr}; }
+
+// ------------------------------------------------------------------ operator
+// Even-odd operator pieces in storage precision P for one parameter set:
+//   B = -1/2 H F,  F = b + c S~,  M_prec = 1 - A^-1 B_oe A^-1 B_eo  (odd sites)
+template <typename P>
+struct Op {
+  using R = typename P::R;
+  using S = typename P::S;
+  dwf_ctx* ctx;
+  const Geometry* g;
+  int Ls;
+  double M5, m, b, c;
+  bool moebius;  // F != 1
+  const S* U[2];
+  const R* E;
+  LaunchCfg cfg;
+
+  Op(dwf_ctx* ctx_, const Geometry* g_, const dwf_params& p, const void* packed_links)
+      : ctx(ctx_), g(g_), Ls(p.Ls), M5(p.M5), m(p.mass), b(p.b), c(p.c) {
+    moebius = !(b == 1.0 && c == 0.0);
+    const S* base = reinterpret_cast<const S*>(packed_links);
+    U[0] = base;
+    U[1] = base + size_t(g->nsites) * 72;
+    E = reinterpret_cast<const R*>(fifth_matrices(ctx, Ls, M5, m, b, c, P::ID));
+    cfg = hop_config(ctx, P::ID, Ls);
+  }
+  const R* em(int slot) const { return E + size_t(slot) * 2 * Ls * Ls; }
+  size_t hb() const { return half_size<P>(g, Ls); }
+  long n5() const { return g->nsites * Ls; }
+
+  // out(out_par) = ax x + Epi . (scale H [F] in)   (H^dag F^dag ... when dag: no prologue)
+  void hop(int out_par, CHalf<P> in, Half<P> out, bool dag, bool pro, double scale, const R* epi,
+           CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr) const {
+    HopArgs<P> a;
+    a.in = in;
+    a.out = out;
+    a.links = U[out_par];
+    a.nbr = g->d_nbr[out_par];
+    a.nsites = g->nsites;
+    a.Ls = Ls;
+    a.scale = R(scale);
+    a.pb = R(b);
+    a.pc = R(c);
+    a.pm = R(m);
+    a.E = epi;
+    a.x = x;
+    a.ax = R(ax);
+    a.norm_partials = partials;
+    DWF_CHECK_LAUNCH(launch_hop<P>(a, dag, pro && moebius, cfg, ctx->stream));
+  }
+  void fifth(CHalf<P> in, Half<P> out, int slot, CHalf<P> x = {nullptr, nullptr}, double ax = 0.0,
+             double* partials = nullptr) const {
+    DWF_CHECK_LAUNCH(launch_fifth<P>(in, out, em(slot), x, R(ax), g->nsites, Ls, partials, ctx->stream));
+  }
+  // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd)
+  void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {
+    hop(0, in, tmp_e, false, true, 1.0, em(E_AINV));
+    hop(1, cv(tmp_e), out, false, true, -0.25, em(E_AINV), in, 1.0, partials);
+  }
+  // M_prec^dag psi = psi - 1/4 F^dag H^dag_oe (A^-dag F^dag) H^dag_eo A^-dag psi
+  void mprec_dag(CHalf<P> in, Half<P> out, Half<P> tmp_o, Half<P> tmp_e, double* partials = nullptr) const {
+    fifth(in, tmp_o, E_AINVDAG);
+    hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
+    hop(1, cv(tmp_e), out, true, false, -0.25, moebius ? em(E_FDAG) : nullptr, in, 1.0, partials);
+  }
+  // full D (or D^dag):  (D psi)_p = A psi_p - 1/2 H F psi_{1-p};  (D^dag psi)_p = A^dag psi_p - 1/2 F^dag H^dag psi_{1-p}
+  void full(CHalf<P> in_e, CHalf<P> in_o, Half<P> out_e, Half<P> out_o, bool dag) const {
+    fifth(in_e, out_e, dag ? E_ADAG : E_A);
+    fifth(in_o, out_o, dag ? E_ADAG : E_A);
+    if (!dag) {
+      hop(0, in_o, out_e, false, true, -0.5, nullptr, cv(out_e), 1.0);
+      hop(1, in_e, out_o, false, true, -0.5, nullptr, cv(out_o), 1.0);
+    } else {
+      hop(0, in_o, out_e, true, false, -0.5, moebius ? em(E_FDAG) : nullptr, cv(out_e), 1.0);
+      hop(1, in_e, out_o, true, false, -0.5, moebius ? em(E_FDAG) : nullptr, cv(out_o), 1.0);
+    }
+  }
+};
+
+// reduction helpers: n partials -> scalar slot
+// per-workgroup FP64 partial sums (room for 4M workgroups)
+inline double* partials_buf(dwf_ctx* ctx) { return reinterpret_cast<double*>(ws_get(ctx, "partials", (size_t(1) << 22) * sizeof(double))); }
+inline double* scalars_buf(dwf_ctx* ctx) { return reinterpret_cast<double*>(ws_get(ctx, "scalars", S_COUNT * sizeof(double))); }
+
+template <typename P>
+double norm2_sync(dwf_ctx* ctx, CHalf<P> a, const Geometry* g, int Ls, int slot = S_TMP0) {
+  double* part = partials_buf(ctx);
+  double* sc = scalars_buf(ctx);
+  const long n5 = g->nsites * Ls;
+  DWF_CHECK_LAUNCH(launch_norm2<P>(a, n5, Ls, part, ctx->stream));
+  DWF_CHECK_LAUNCH(launch_reduce(part, reduction_blocks(n5), 1, sc, slot, 0, ctx->stream));
+  return read_scalar(ctx, sc, slot);
+}
+
+}  // namespace dwf

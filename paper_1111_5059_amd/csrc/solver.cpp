@@ -1,0 +1,437 @@
+// Solvers on the even-odd DWF/Moebius system:
+//   * CG on the normal equations of M_prec (CGNR), optionally with iterations
+//     in FP32 / FP16 / BF16 storage and FP64 reliable updates (Sleijpen and van
+//     der Vorst 1996; as used for lattice QCD on GPUs by Clark et al. 2010) --
+//     FP64 CG scalars, FP64 solution accumulator, FP64 true residual;
+//   * the Moebius-accelerated DWF solve (Sec. 4 algorithm, Sec. 5 defect
+//     correction, Table 1 operation counting);
+//   * the fermion force and the force-gradient step (Sec. 2).
+#include <chrono>
+#include "runtime.hpp"
+#include "solver.hpp"
+
+namespace dwf {
+
+using Clock = std::chrono::steady_clock;
+
+template <typename P>
+static CHalf<P> chalf_at(const void* base, size_t off, const Geometry* g, int Ls) {
+  return chview<P>(reinterpret_cast<const char*>(base) + off, g, Ls);
+}
+template <typename P>
+static Half<P> half_at(void* base, size_t off, const Geometry* g, int Ls) {
+  return hview<P>(reinterpret_cast<char*>(base) + off, g, Ls);
+}
+
+static std::string pname(int prec) {
+  static const char* n[4] = {"f64", "f32", "f16", "bf16"};
+  return n[prec & 3];
+}
+
+// packed links of precision prec converted from the packed FP64 links
+static const void* links_in(dwf_ctx* ctx, const Geometry* g, const void* U64, int prec, const std::string& tag) {
+  if (prec == DWF_FP64) return U64;
+  const long n = 2 * g->nsites * 72;
+  void* dst;
+  switch (prec) {
+    case DWF_FP32:
+      dst = ws_get(ctx, tag + ".U32", n * sizeof(P32::S));
+      DWF_CHECK_LAUNCH((launch_convert_links<P64, P32>(reinterpret_cast<const double2*>(U64),
+                                                        reinterpret_cast<P32::S*>(dst), n, ctx->stream)));
+      return dst;
+    case DWF_FP16:
+      dst = ws_get(ctx, tag + ".U16", n * sizeof(P16::S));
+      DWF_CHECK_LAUNCH((launch_convert_links<P64, P16>(reinterpret_cast<const double2*>(U64),
+                                                        reinterpret_cast<P16::S*>(dst), n, ctx->stream)));
+      return dst;
+    default:
+      dst = ws_get(ctx, tag + ".Ub16", n * sizeof(PB16::S));
+      DWF_CHECK_LAUNCH((launch_convert_links<P64, PB16>(reinterpret_cast<const double2*>(U64),
+                                                         reinterpret_cast<PB16::S*>(dst), n, ctx->stream)));
+      return dst;
+  }
+}
+
+// ------------------------------------------------------------------ CG on M^dag M
+// Solves M^dag M x = rhs (odd sites) until ||rhs - M^dag M x|| <= tol_n ||rhs||.
+// x (FP64) holds the initial guess.  Iterations in storage precision Pi; for
+// Pi != FP64 the iterate increment accumulates in FP32 and is folded into the
+// FP64 x at every reliable update, where the residual is recomputed in FP64.
+template <typename Pi>
+static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf<P64> rhs, Half<P64> x,
+                     double tol_n, int maxit, double delta, const std::string& tag, SolveStats* st) {
+  const Geometry* g = op64.g;
+  const int Ls = op64.Ls;
+  const long n5 = g->nsites * Ls;
+  const size_t hb64 = half_size<P64>(g, Ls), hbi = half_size<Pi>(g, Ls);
+  double* part = partials_buf(ctx);
+  double* sc = scalars_buf(ctx);
+  hipStream_t s = ctx->stream;
+  constexpr bool MIXED = !std::is_same<Pi, P64>::value;
+  using PX = typename std::conditional<MIXED, P32, P64>::type;
+  constexpr bool RESTART = std::is_same<Pi, PB16>::value;
+
+  // FP64 residual r_hi = rhs - M^dag M x
+  Half<P64> rhi = hview<P64>(ws_get(ctx, tag + ".rhi", hb64), g, Ls);
+  Half<P64> t64a = hview<P64>(ws_get(ctx, tag + ".t64a", hb64), g, Ls);
+  Half<P64> t64b = hview<P64>(ws_get(ctx, tag + ".t64b", hb64), g, Ls);
+  Half<P64> t64c = hview<P64>(ws_get(ctx, tag + ".t64c", hb64), g, Ls);
+  auto true_residual = [&]() -> double {
+    op64.mprec(cv(x), t64a, t64b);
+    op64.mprec_dag(cv(t64a), rhi, t64b, t64c);
+    DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, rhs, -1.0, rhi, n5, Ls, s));
+    return norm2_sync<P64>(ctx, cv(rhi), g, Ls);
+  };
+  const double rhs2 = norm2_sync<P64>(ctx, rhs, g, Ls);
+  if (rhs2 == 0.0) {
+    DWF_CHECK_LAUNCH(launch_zero(x.data, hb64, s));
+    return 0;
+  }
+  const double target = tol_n * tol_n * rhs2;
+  double rr = true_residual();
+  if (!std::isfinite(rr)) throw Error{DWF_ERR_NAN, "non-finite residual at CG start"};
+  if (rr <= target) return 0;
+
+  // inner vectors
+  Half<Pi> r = hview<Pi>(MIXED ? ws_get(ctx, tag + ".r." + pname(Pi::ID), hbi) : (void*)rhi.data, g, Ls);
+  if (!MIXED) r = hview<Pi>((void*)rhi.data, g, Ls);
+  Half<Pi> p = hview<Pi>(ws_get(ctx, tag + ".p." + pname(Pi::ID), hbi), g, Ls);
+  Half<Pi> q = hview<Pi>(ws_get(ctx, tag + ".q." + pname(Pi::ID), hbi), g, Ls);
+  Half<Pi> Ap = hview<Pi>(ws_get(ctx, tag + ".Ap." + pname(Pi::ID), hbi), g, Ls);
+  Half<Pi> te = hview<Pi>(ws_get(ctx, tag + ".te." + pname(Pi::ID), hbi), g, Ls);
+  Half<Pi> to = hview<Pi>(ws_get(ctx, tag + ".to." + pname(Pi::ID), hbi), g, Ls);
+  Half<PX> xl = hview<PX>(MIXED ? ws_get(ctx, tag + ".xlo", half_size<PX>(g, Ls)) : (void*)x.data, g, Ls);
+  if (MIXED) {
+    DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
+    DWF_CHECK_LAUNCH(launch_zero(xl.data, half_size<PX>(g, Ls), s));
+  }
+  // p = r
+  DWF_CHECK_LAUNCH(launch_axpby<Pi>(1.0, cv(r), 0.0, p, n5, Ls, s));
+  DWF_CHECK_LAUNCH(launch_set_scalar(sc, S_RR, rr, s));
+  double rr_max = rr;
+  const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
+  const int nb_red = reduction_blocks(n5);
+  int it = 0;
+  while (it < maxit) {
+    // q = M p, |q|^2 -> alpha = rr / |q|^2
+    opi.mprec(cv(p), q, te, part);
+    DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_QQ, 1, s));
+    opi.mprec_dag(cv(q), Ap, to, te);
+    DWF_CHECK_LAUNCH((launch_cg_update<Pi, PX>(xl, cv(p), r, cv(Ap), sc, n5, Ls, part, s)));
+    DWF_CHECK_LAUNCH(launch_reduce(part, nb_red, 1, sc, S_RRNEW, 0, s));
+    double rr_new = read_scalar(ctx, sc, S_RRNEW);
+    ++it;
+    if (!std::isfinite(rr_new)) throw Error{DWF_ERR_NAN, "non-finite residual in CG iteration"};
+    if (MIXED && (rr_new < delta * delta * rr_max || rr_new <= target)) {
+      // reliable update: fold the FP32 increment into the FP64 solution, recompute r in FP64
+      DWF_CHECK_LAUNCH(launch_accumulate<PX>(x, xl, n5, Ls, s));
+      rr_new = true_residual();
+      DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
+      rr_max = rr_new;
+      st->reliable_updates++;
+      if (rr_new > target && RESTART) {
+        // BF16 (8-bit mantissa): the retained direction loses conjugacy and CG stagnates;
+        // restart the Krylov space from the recomputed residual.
+        DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, 0.0, sc, rr_new, n5, Ls, s));
+        rr = rr_new;
+        continue;
+      }
+    }
+    if (rr_new <= target) {
+      rr = rr_new;
+      break;
+    }
+    const double beta = rr_new / rr;
+    DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, beta, sc, rr_new, n5, Ls, s));
+    rr = rr_new;
+    if (rr > rr_max) rr_max = rr;
+  }
+  if (MIXED) DWF_CHECK_LAUNCH(launch_accumulate<PX>(x, xl, n5, Ls, s));
+  st->iters += it;
+  st->last_rel = std::sqrt(rr / rhs2);
+  return rr <= target ? 0 : 1;
+}
+
+template <typename Pi>
+static int cg_normal_dispatch(dwf_ctx* ctx, const Op<P64>& op64, const dwf_params& p, const void* U64,
+                              CHalf<P64> rhs, Half<P64> x, double tol_n, int maxit, double delta,
+                              const std::string& tag, SolveStats* st) {
+  const void* Ui = links_in(ctx, op64.g, U64, Pi::ID, tag);
+  Op<Pi> opi(ctx, op64.g, p, Ui);
+  return cg_normal<Pi>(ctx, op64, opi, rhs, x, tol_n, maxit, delta, tag, st);
+}
+
+int normal_solve(dwf_ctx* ctx, const dwf_params& p, const void* U64, CHalf<P64> rhs, Half<P64> x, double tol_n,
+                 int maxit, double delta, const std::string& tag, SolveStats* st) {
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  Op<P64> op64(ctx, g, p, U64);
+  switch (p.prec_inner) {
+    case DWF_FP64: return cg_normal_dispatch<P64>(ctx, op64, p, U64, rhs, x, tol_n, maxit, delta, tag, st);
+    case DWF_FP32: return cg_normal_dispatch<P32>(ctx, op64, p, U64, rhs, x, tol_n, maxit, delta, tag, st);
+    case DWF_FP16: return cg_normal_dispatch<P16>(ctx, op64, p, U64, rhs, x, tol_n, maxit, delta, tag, st);
+    default: return cg_normal_dispatch<PB16>(ctx, op64, p, U64, rhs, x, tol_n, maxit, delta, tag, st);
+  }
+}
+
+// ------------------------------------------------------------------ full-system solve
+// D(m) x = b through the Schur complement on odd sites:
+//   b'_o = A^-1 (b_o - B_oe A^-1 b_e),  M x_o = b'_o  (CGNR),  x_e = A^-1 (b_e - B_eo x_o),
+// tightening the normal-equation tolerance until ||b - D x|| / ||b|| <= tol.
+int solve_full(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b, void* x, double tol, int maxit,
+               double delta, const std::string& tag, dwf_solve_info* info) {
+  const auto t0 = Clock::now();
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const int Ls = p.Ls;
+  const long n5 = g->nsites * Ls;
+  const size_t hb = half_size<P64>(g, Ls);
+  hipStream_t s = ctx->stream;
+  Op<P64> op(ctx, g, p, U64);
+  CHalf<P64> be = chalf_at<P64>(b, 0, g, Ls), bo = chalf_at<P64>(b, hb, g, Ls);
+  Half<P64> xe = half_at<P64>(x, 0, g, Ls), xo = half_at<P64>(x, hb, g, Ls);
+  Half<P64> te = hview<P64>(ws_get(ctx, tag + ".se", hb), g, Ls);
+  Half<P64> to = hview<P64>(ws_get(ctx, tag + ".so", hb), g, Ls);
+  Half<P64> bp = hview<P64>(ws_get(ctx, tag + ".bp", hb), g, Ls);
+  Half<P64> rhs = hview<P64>(ws_get(ctx, tag + ".rhs", hb), g, Ls);
+  Half<P64> t2 = hview<P64>(ws_get(ctx, tag + ".t2", hb), g, Ls);
+  void* rfull = ws_get(ctx, tag + ".rfull", 2 * hb);
+  Half<P64> re = half_at<P64>(rfull, 0, g, Ls), ro = half_at<P64>(rfull, hb, g, Ls);
+
+  const double b2 = norm2_sync<P64>(ctx, be, g, Ls) + norm2_sync<P64>(ctx, bo, g, Ls);
+  if (!std::isfinite(b2)) throw Error{DWF_ERR_NAN, "non-finite source"};
+  SolveStats st;
+  int status = 0;
+  double rel = 0.0;
+  if (b2 == 0.0) {
+    DWF_CHECK_LAUNCH(launch_zero(x, 2 * hb, s));
+  } else {
+    // source preparation
+    op.fifth(be, te, E_AINV);                                  // A^-1 b_e
+    op.hop(1, cv(te), to, false, true, 0.5, nullptr, bo, 1.0);  // b_o - B_oe A^-1 b_e
+    op.fifth(cv(to), bp, E_AINV);                              // b'_o
+    op.mprec_dag(cv(bp), rhs, te, t2);                         // M^dag b'
+    double tol_n = tol;
+    status = 1;
+    for (int attempt = 0; attempt < 12; ++attempt) {
+      const int left = maxit - st.iters;
+      if (left <= 0) break;
+      normal_solve(ctx, p, U64, cv(rhs), xo, tol_n, left, delta, tag + ".cg", &st);
+      // x_e = A^-1 (b_e - B_eo x_o)
+      op.hop(0, cv(xo), te, false, true, 0.5, nullptr, be, 1.0);
+      op.fifth(cv(te), xe, E_AINV);
+      // true residual of the full system
+      op.full(cv(xe), cv(xo), re, ro, false);
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, be, -1.0, re, n5, Ls, s));
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, bo, -1.0, ro, n5, Ls, s));
+      const double r2 = norm2_sync<P64>(ctx, cv(re), g, Ls) + norm2_sync<P64>(ctx, cv(ro), g, Ls);
+      rel = std::sqrt(r2 / b2);
+      if (!std::isfinite(rel)) throw Error{DWF_ERR_NAN, "non-finite true residual"};
+      if (rel <= tol) {
+        status = 0;
+        break;
+      }
+      tol_n *= std::max(0.02, std::min(0.5, 0.5 * tol / rel));
+      st.restarts++;
+    }
+  }
+  DWF_CHECK_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = st.iters;
+    info->reliable_updates = st.reliable_updates;
+    info->restarts = st.restarts;
+    info->true_rel_resid = rel;
+    info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    info->wilson_apps = (long long)st.iters * Ls;
+  }
+  return status;
+}
+
+// ------------------------------------------------------------------ MADWF
+// Sec. 4 algorithm with Sec. 5 defect correction.  target: Shamir DWF D(m), Ls = L;
+// inner: Moebius D'(m), Ls = L'.  Per step k:
+//   r = b - D(m) x;  c = P^-1 D(1)^-1 r;  z = D'(m)^-1 D'(1) P' (c_1, 0, .., 0);
+//   y'_1 = (P'^-1 z)_1;  w = P^-1 D(1)^-1 D(m) P (-y'_1, c_2, .., c_L);  w_1 = y'_1;  x += P w.
+// then a warm-started DWF solve to the final tolerance.
+int madwf(dwf_ctx* ctx, const dwf_params& pt, const dwf_params& pi, const void* U64, const void* b, void* x,
+          dwf_madwf_info* info) {
+  const auto t0 = Clock::now();
+  const Geometry* g = geometry(ctx, pt.dims, pt.tbc);
+  const int L = pt.Ls, Lp = pi.Ls;
+  const size_t hb = half_size<P64>(g, L), hbp = half_size<P64>(g, Lp);
+  const long ns = g->nsites;
+  hipStream_t s = ctx->stream;
+  const double delta = info->delta > 0 ? info->delta : 0.1;
+  const int maxit = info->maxit > 0 ? info->maxit : 100000;
+  dwf_params ppv = pt;
+  ppv.mass = 1.0;
+  ppv.prec_inner = info->prec_pv;
+  dwf_params pipv = pi;
+  pipv.mass = 1.0;
+  Op<P64> opt(ctx, g, pt, U64);
+  Op<P64> opi1(ctx, g, pipv, U64);
+  void* r = ws_get(ctx, "madwf.r", 2 * hb);
+  void* c = ws_get(ctx, "madwf.c", 2 * hb);
+  void* t = ws_get(ctx, "madwf.t", 2 * hb);
+  void* w = ws_get(ctx, "madwf.w", 2 * hb);
+  void* cp = ws_get(ctx, "madwf.cp", 2 * hbp);
+  void* zp = ws_get(ctx, "madwf.zp", 2 * hbp);
+  void* yp = ws_get(ctx, "madwf.yp", 2 * hbp);
+  void* rp = ws_get(ctx, "madwf.rp", 2 * hbp);
+  auto H = [&](void* base, int par, int Lx, size_t hbx) { return half_at<P64>(base, par ? hbx : 0, g, Lx); };
+  auto CH = [&](const void* base, int par, int Lx, size_t hbx) { return chalf_at<P64>(base, par ? hbx : 0, g, Lx); };
+  auto pshift = [&](const void* in, void* out, int inverse, int Lx, size_t hbx) {
+    for (int par = 0; par < 2; ++par)
+      DWF_CHECK_LAUNCH(launch_pshift(CH(in, par, Lx, hbx), H(out, par, Lx, hbx), inverse, ns, Lx, s));
+  };
+  auto residual = [&](void* out) -> double {  // out = b - D(m) x, returns |out|^2
+    opt.full(CH(x, 0, L, hb), CH(x, 1, L, hb), H(out, 0, L, hb), H(out, 1, L, hb), false);
+    double r2 = 0.0;
+    for (int par = 0; par < 2; ++par) {
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, CH(b, par, L, hb), -1.0, H(out, par, L, hb), ns * L, L, s));
+      r2 += norm2_sync<P64>(ctx, CH(out, par, L, hb), g, L);
+    }
+    return r2;
+  };
+  double b2 = 0.0;
+  for (int par = 0; par < 2; ++par) b2 += norm2_sync<P64>(ctx, CH(b, par, L, hb), g, L);
+  if (!std::isfinite(b2)) throw Error{DWF_ERR_NAN, "non-finite source"};
+  DWF_CHECK_LAUNCH(launch_zero(x, 2 * hb, s));
+  info->pv_iters = info->mobius_iters = info->final_iters = info->n_pv = info->n_mobius = 0;
+  info->seconds_pv = info->seconds_mobius = info->seconds_final = 0.0;
+  dwf_solve_info si;
+  const int ndc = std::min(info->n_dc, 8);
+  for (int k = 0; k < ndc; ++k) {
+    residual(r);
+    // c = P^-1 D(1)^-1 r
+    DWF_CHECK_LAUNCH(launch_zero(t, 2 * hb, s));
+    std::memset(&si, 0, sizeof(si));
+    solve_full(ctx, ppv, U64, r, t, info->tol_pv, maxit, delta, "pv", &si);
+    info->pv_iters += si.iters; info->n_pv++; info->seconds_pv += si.seconds;
+    pshift(t, c, 1, L, hb);
+    // rhs' = D'(1) P' (c_1, 0, ..., 0)
+    DWF_CHECK_LAUNCH(launch_zero(cp, 2 * hbp, s));
+    for (int par = 0; par < 2; ++par)
+      DWF_CHECK_LAUNCH(launch_slice_copy(CH(c, par, L, hb), L, 0, H(cp, par, Lp, hbp), Lp, 0, 1.0, ns, s));
+    pshift(cp, zp, 0, Lp, hbp);
+    opi1.full(CH(zp, 0, Lp, hbp), CH(zp, 1, Lp, hbp), H(rp, 0, Lp, hbp), H(rp, 1, Lp, hbp), false);
+    // D'(m) z = rhs'
+    DWF_CHECK_LAUNCH(launch_zero(zp, 2 * hbp, s));
+    std::memset(&si, 0, sizeof(si));
+    solve_full(ctx, pi, U64, rp, zp, info->tol_mobius, maxit, delta, "mob", &si);
+    info->mobius_iters += si.iters; info->n_mobius++; info->seconds_mobius += si.seconds;
+    pshift(zp, yp, 1, Lp, hbp);  // y' = P'^-1 z ; y'_1 = slice 0
+    // v = (-y'_1, c_2, ..., c_L) in c ; t = D(m) P v
+    for (int par = 0; par < 2; ++par)
+      DWF_CHECK_LAUNCH(launch_slice_copy(CH(yp, par, Lp, hbp), Lp, 0, H(c, par, L, hb), L, 0, -1.0, ns, s));
+    pshift(c, w, 0, L, hb);
+    opt.full(CH(w, 0, L, hb), CH(w, 1, L, hb), H(t, 0, L, hb), H(t, 1, L, hb), false);
+    // w = P^-1 D(1)^-1 t
+    DWF_CHECK_LAUNCH(launch_zero(w, 2 * hb, s));
+    std::memset(&si, 0, sizeof(si));
+    solve_full(ctx, ppv, U64, t, w, info->tol_pv, maxit, delta, "pv", &si);
+    info->pv_iters += si.iters; info->n_pv++; info->seconds_pv += si.seconds;
+    pshift(w, c, 1, L, hb);
+    // replace the first slice by y'_1, back to the domain-wall basis, add to x
+    for (int par = 0; par < 2; ++par)
+      DWF_CHECK_LAUNCH(launch_slice_copy(CH(yp, par, Lp, hbp), Lp, 0, H(c, par, L, hb), L, 0, 1.0, ns, s));
+    pshift(c, t, 0, L, hb);
+    for (int par = 0; par < 2; ++par)
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, CH(t, par, L, hb), 1.0, H(x, par, L, hb), ns * L, L, s));
+    info->resid_after_dc[k] = std::sqrt(residual(r) / b2);
+  }
+  dwf_params pf = pt;
+  pf.prec_inner = info->prec_final;
+  std::memset(&si, 0, sizeof(si));
+  const int st = solve_full(ctx, pf, U64, b, x, info->tol, maxit, delta, "final", &si);
+  info->final_iters = si.iters;
+  info->seconds_final = si.seconds;
+  info->true_rel_resid = si.true_rel_resid;
+  info->wilson_apps = (long long)info->pv_iters * L + (long long)info->mobius_iters * Lp + (long long)info->final_iters * L;
+  info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+  return st;
+}
+
+// ------------------------------------------------------------------ force
+// S = phi^dag (M^dag M)^-1 phi.  X = (M^dag M)^-1 phi (warm start from x_io), Y = M X,
+// X_e = A^-1 B_eo X, Y_o' = A^-dag Y, Y_e' = A^-dag B_oe^dag Y_o', W = F (X, X_e),
+// Z = (Y_e', Y_o'); one thread per link contracts them into F_mu(x) or G_mu(x).
+static double force_at(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const void* phi, void* X, void* Fout,
+                       int kind, double tol_n, int maxit, double delta, SolveStats* st) {
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const int Ls = p.Ls;
+  const size_t hb = half_size<P64>(g, Ls);
+  hipStream_t s = ctx->stream;
+  void* U64 = ws_get(ctx, "force.U64", 2 * g->nsites * 72 * sizeof(double2));
+  DWF_CHECK_LAUNCH(launch_pack_gauge<P64>(g->tables(), reinterpret_cast<const double2*>(Unat),
+                                          reinterpret_cast<double2*>(U64), s));
+  Op<P64> op(ctx, g, p, U64);
+  CHalf<P64> ph = chview<P64>(phi, g, Ls);
+  Half<P64> Xo = hview<P64>(X, g, Ls);
+  normal_solve(ctx, p, U64, ph, Xo, tol_n, maxit, delta, "force.cg", st);
+  // S = Re <phi, X>
+  double* part = partials_buf(ctx);
+  double* sc = scalars_buf(ctx);
+  DWF_CHECK_LAUNCH(launch_dot<P64>(ph, cv(Xo), g->nsites * Ls, Ls, part, s));
+  DWF_CHECK_LAUNCH(launch_reduce(part, reduction_blocks(g->nsites * Ls), 2, sc, S_TMP1, 0, s));
+  const double S = read_scalar(ctx, sc, S_TMP1);
+  Half<P64> Y = hview<P64>(ws_get(ctx, "force.Y", hb), g, Ls);
+  Half<P64> Xe = hview<P64>(ws_get(ctx, "force.Xe", hb), g, Ls);
+  Half<P64> Zo = hview<P64>(ws_get(ctx, "force.Zo", hb), g, Ls);
+  Half<P64> Ze = hview<P64>(ws_get(ctx, "force.Ze", hb), g, Ls);
+  Half<P64> We = hview<P64>(ws_get(ctx, "force.We", hb), g, Ls);
+  Half<P64> Wo = hview<P64>(ws_get(ctx, "force.Wo", hb), g, Ls);
+  Half<P64> tmp = hview<P64>(ws_get(ctx, "force.tmp", hb), g, Ls);
+  op.mprec(cv(Xo), Y, tmp);                                            // Y = M X
+  op.hop(0, cv(Xo), Xe, false, true, -0.5, op.em(E_AINV));             // X_e = A^-1 B_eo X
+  op.fifth(cv(Y), Zo, E_AINVDAG);                                      // Y_o' = A^-dag Y
+  op.hop(0, cv(Zo), Ze, true, false, -0.5, op.em(E_AINVDAG_FDAG));     // Y_e' = A^-dag B_oe^dag Y_o'
+  op.fifth(cv(Xo), Wo, E_F);                                           // W_o = F X
+  op.fifth(cv(Xe), We, E_F);                                           // W_e = F X_e
+  DWF_CHECK_LAUNCH(launch_force(g->tables(), Ls, cv(We), cv(Wo), cv(Ze), cv(Zo),
+                                reinterpret_cast<const double2*>(Unat), p.tbc, p.dims, kind,
+                                reinterpret_cast<double2*>(Fout), s));
+  return S;
+}
+
+int fermion_force(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const void* phi, void* F, double* S,
+                  double tau_fg, int out_kind, void* x_io, dwf_solve_info* info) {
+  const auto t0 = Clock::now();
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const int Ls = p.Ls;
+  const size_t hb = half_size<P64>(g, Ls);
+  hipStream_t s = ctx->stream;
+  const double tol = info && info->tol > 0 ? info->tol : 1e-12;
+  const double delta = info && info->delta > 0 ? info->delta : 0.1;
+  const int maxit = info && info->maxit > 0 ? info->maxit : 100000;
+  void* X = ws_get(ctx, "force.X", hb);
+  if (x_io) DWF_CHECK_HIP(hipMemcpyAsync(X, x_io, hb, hipMemcpyDeviceToDevice, s));
+  else DWF_CHECK_LAUNCH(launch_zero(X, hb, s));
+  SolveStats st;
+  double Sv;
+  if (tau_fg > 0.0) {
+    // force-gradient step: F1 at U; U' = exp(-tau^2/24 F1) U; force at U' from X(U)
+    const long nlinks = 4 * g->V;
+    void* F1 = ws_get(ctx, "force.F1", nlinks * 9 * sizeof(double2));
+    void* Up = ws_get(ctx, "force.Uprime", nlinks * 9 * sizeof(double2));
+    force_at(ctx, p, Unat, phi, X, F1, 0, tol, maxit, delta, &st);
+    const int it1 = st.iters;
+    DWF_CHECK_LAUNCH(launch_fg_update(reinterpret_cast<const double2*>(F1), reinterpret_cast<const double2*>(Unat),
+                                      tau_fg * tau_fg / 24.0, reinterpret_cast<double2*>(Up), nlinks, s));
+    Sv = force_at(ctx, p, Up, phi, X, F, out_kind, tol, maxit, delta, &st);
+    if (info) info->iters_first = it1;
+  } else {
+    Sv = force_at(ctx, p, Unat, phi, X, F, out_kind, tol, maxit, delta, &st);
+  }
+  if (x_io) DWF_CHECK_HIP(hipMemcpyAsync(x_io, X, hb, hipMemcpyDeviceToDevice, s));
+  DWF_CHECK_HIP(hipStreamSynchronize(s));
+  if (S) *S = Sv;
+  if (info) {
+    info->iters = st.iters;
+    info->reliable_updates = st.reliable_updates;
+    info->true_rel_resid = st.last_rel;
+    info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    info->wilson_apps = (long long)st.iters * Ls;
+  }
+  return 0;
+}
+
+}  // namespace dwf

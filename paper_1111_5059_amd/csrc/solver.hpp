@@ -1,0 +1,24 @@
+// Solver entry points used by the C ABI.
+#pragma once
+#include <string>
+#include "runtime.hpp"
+
+namespace dwf {
+
+struct SolveStats {
+  int iters = 0;
+  int reliable_updates = 0;
+  int restarts = 0;
+  double last_rel = 0.0;
+};
+
+int normal_solve(dwf_ctx* ctx, const dwf_params& p, const void* U64, CHalf<P64> rhs, Half<P64> x, double tol_n,
+                 int maxit, double delta, const std::string& tag, SolveStats* st);
+int solve_full(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b, void* x, double tol, int maxit,
+               double delta, const std::string& tag, dwf_solve_info* info);
+int madwf(dwf_ctx* ctx, const dwf_params& pt, const dwf_params& pi, const void* U64, const void* b, void* x,
+          dwf_madwf_info* info);
+int fermion_force(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const void* phi, void* F, double* S,
+                  double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
+
+}  // namespace dwf

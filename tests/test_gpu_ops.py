@@ -1,0 +1,165 @@
+"""Parity of every operator application of the HIP path against the FP64 oracle.
+
+FP64 within 1e-12 relative (max-norm), FP32 within 1e-5 per application; FP16
+(with per-site norm) and BF16 storage are gated at their format's precision
+(4e-3 and 3e-2) and their error is printed.  Extents are chosen so that the
+half-lattice spans several workgroups with a ragged last one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import PREC_TOL, gpu_ctx, mask, rel_err
+
+pytestmark = pytest.mark.gpu
+
+# (dims, Ls): 720 and 72 checkerboard sites -> ragged last workgroup for Ls = 8, 12, 16
+CASES = [((6, 4, 6, 10), 8), ((6, 2, 2, 6), 12), ((4, 4, 4, 4), 16), ((2, 2, 2, 2), 4)]
+
+
+@pytest.fixture(scope="module")
+def env():
+    return gpu_ctx()
+
+
+def make(dims, Ls, seed, eps=0.5):
+    U = synth.random_links(dims, eps, seed)
+    psi = synth.gaussian_spinor(dims, Ls, seed + 1)
+    return U, psi
+
+
+@pytest.mark.parametrize("dims,Ls", CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_hop_parity(env, ora, dims, Ls, prec, dagger):
+    dwf, ctx = env
+    P = dwf.PREC_NAMES[prec]
+    tbc = 1 if Ls == 12 else 0
+    U, psi = make(dims, Ls, 300 + Ls)
+    lat = dwf.Lattice(ctx, dims, Ls, tbc=tbc)
+    Ug = lat.pack_gauge(U, P)
+    p = lat.params(P)
+    po = ora.params(dims, Ls, tbc=tbc)
+    for out_par in (0, 1):
+        kin = dwf.KIND_ODD if out_par == 0 else dwf.KIND_EVEN
+        kout = dwf.KIND_EVEN if out_par == 0 else dwf.KIND_ODD
+        src = lat.pack(psi, kin, P)
+        dst = lat.empty(kout, P)
+        dwf.dwf_dslash(ctx, p, Ug, src, dst, dwf.OP_HOP, out_par, dagger)
+        got = lat.unpack_np(dst, kout, P)
+        ref = ora.hop5(po, U, mask(psi, dims, 1 - out_par), dagger=dagger, out_parity=out_par)
+        err = rel_err(got, ref)
+        print(f"hop {prec} dims={dims} Ls={Ls} dag={dagger} par={out_par}: rel err {err:.2e}")
+        assert err < PREC_TOL[prec]
+
+
+@pytest.mark.parametrize("dims,Ls", CASES[:3])
+@pytest.mark.parametrize("bc", [(1.0, 0.0), (1.5, 0.5)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+def test_mprec_parity(env, ora, dims, Ls, bc, prec):
+    dwf, ctx = env
+    P = dwf.PREC_NAMES[prec]
+    U, psi = make(dims, Ls, 400 + Ls)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.05, b=bc[0], c=bc[1], tbc=1)
+    Ug = lat.pack_gauge(U, P)
+    p = lat.params(P)
+    po = ora.params(dims, Ls, mass=0.05, b=bc[0], c=bc[1], tbc=1)
+    psio = mask(psi, dims, 1)
+    src = lat.pack(psio, dwf.KIND_ODD, P)
+    for dagger in (False, True):
+        dst = lat.empty(dwf.KIND_ODD, P)
+        dwf.mobius_dslash(ctx, p, Ug, src, dst, dwf.OP_MPREC, 1, dagger)
+        got = lat.unpack_np(dst, dwf.KIND_ODD, P)
+        ref = ora.mprec(po, U, psio, dagger=dagger)
+        err = rel_err(got, ref)
+        print(f"mprec {prec} bc={bc} dims={dims} Ls={Ls} dag={dagger}: rel err {err:.2e}")
+        assert err < PREC_TOL[prec]
+
+
+@pytest.mark.parametrize("dims,Ls", CASES)
+@pytest.mark.parametrize("bc", [(1.0, 0.0), (1.5, 0.5)])
+def test_full_operator_parity(env, ora, dims, Ls, bc):
+    dwf, ctx = env
+    U, psi = make(dims, Ls, 500 + Ls)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.02, b=bc[0], c=bc[1])
+    Ug = lat.pack_gauge(U)
+    p = lat.params()
+    po = ora.params(dims, Ls, mass=0.02, b=bc[0], c=bc[1])
+    src = lat.pack(psi)
+    for dagger in (False, True):
+        dst = lat.empty(dwf.KIND_FULL)
+        dwf.mobius_dslash(ctx, p, Ug, src, dst, dwf.OP_FULL, 0, dagger)
+        got = lat.unpack_np(dst)
+        ref = ora.dwf(po, U, psi, dagger=dagger)
+        err = rel_err(got, ref)
+        print(f"D bc={bc} dims={dims} Ls={Ls} dag={dagger}: rel err {err:.2e}")
+        assert err < 1e-12
+
+
+@pytest.mark.parametrize("Ls,bc,m", [(8, (1.0, 0.0), 0.01), (16, (1.5, 0.5), 0.005), (12, (2.0, 1.0), 1.0)])
+def test_fifth_blocks_parity(env, ora, Ls, bc, m):
+    dwf, ctx = env
+    dims = (4, 4, 2, 2)
+    psi = synth.gaussian_spinor(dims, Ls, 600 + Ls)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=m, b=bc[0], c=bc[1])
+    U = synth.random_links(dims, 0.5, 601)
+    Ug = lat.pack_gauge(U)
+    p = lat.params()
+    po = ora.params(dims, Ls, mass=m, b=bc[0], c=bc[1])
+    psie = mask(psi, dims, 0)
+    src = lat.pack(psie, dwf.KIND_EVEN)
+    for op, which in ((dwf.OP_A, "A"), (dwf.OP_AINV, "Ainv")):
+        for dagger in (False, True):
+            dst = lat.empty(dwf.KIND_EVEN)
+            dwf.mobius_dslash(ctx, p, Ug, src, dst, op, 0, dagger)
+            got = lat.unpack_np(dst, dwf.KIND_EVEN)
+            ref = mask(ora.fifth(po, psie, which + ("dag" if dagger else "")), dims, 0)
+            assert rel_err(got, ref) < 1e-13
+
+
+def test_moebius_hop_includes_input_factor(env, ora):
+    """mobius_dslash HOP applies H (b + c S~) (and its adjoint F^dag H^dag)."""
+    dwf, ctx = env
+    dims, Ls = (4, 4, 4, 6), 8
+    U, psi = make(dims, Ls, 700)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.1, b=1.5, c=0.5)
+    Ug = lat.pack_gauge(U)
+    p = lat.params()
+    po = ora.params(dims, Ls, mass=0.1, b=1.5, c=0.5)
+    psio = mask(psi, dims, 1)
+    src = lat.pack(psio, dwf.KIND_ODD)
+    dst = lat.empty(dwf.KIND_EVEN)
+    dwf.mobius_dslash(ctx, p, Ug, src, dst, dwf.OP_HOP, 0, False)
+    ref = ora.hop5(po, U, ora.fifth(po, psio, "F"), out_parity=0)
+    assert rel_err(lat.unpack_np(dst, dwf.KIND_EVEN), ref) < 1e-12
+    dwf.mobius_dslash(ctx, p, Ug, src, dst, dwf.OP_HOP, 0, True)
+    ref = mask(ora.fifth(po, ora.hop5(po, U, psio, dagger=True), "Fdag"), dims, 0)
+    assert rel_err(lat.unpack_np(dst, dwf.KIND_EVEN), ref) < 1e-12
+
+
+def test_moebius_b1_c0_is_shamir(env):
+    dwf, ctx = env
+    dims, Ls = (4, 4, 4, 4), 8
+    U, psi = make(dims, Ls, 800)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.01)
+    Ug = lat.pack_gauge(U)
+    src = lat.pack(mask(psi, dims, 1), dwf.KIND_ODD)
+    a, b = lat.empty(dwf.KIND_ODD), lat.empty(dwf.KIND_ODD)
+    dwf.dwf_dslash(ctx, lat.params(), Ug, src, a, dwf.OP_MPREC, 1, False)
+    dwf.mobius_dslash(ctx, lat.params(), Ug, src, b, dwf.OP_MPREC, 1, False)
+    assert rel_err(lat.unpack_np(a, dwf.KIND_ODD), lat.unpack_np(b, dwf.KIND_ODD)) == 0.0
+
+
+def test_pack_roundtrip_and_errors(env):
+    dwf, ctx = env
+    dims, Ls = (4, 2, 2, 2), 4
+    psi = synth.gaussian_spinor(dims, Ls, 900)
+    lat = dwf.Lattice(ctx, dims, Ls)
+    assert rel_err(lat.unpack_np(lat.pack(psi)), psi) == 0.0
+    bad = dwf.params((3, 4, 4, 4), 4)
+    with pytest.raises(dwf.DwfError) as e:
+        dwf.dwf_dslash(ctx, bad, 1, 2, 3, dwf.OP_HOP, 0, False)
+    assert e.value.code == dwf.DWF_ERR_ARG
+    src = lat.pack(psi)
+    with pytest.raises(dwf.DwfError):
+        dwf.dwf_dslash(ctx, lat.params(), src, src, src, dwf.OP_HOP, 0, False)
