@@ -185,11 +185,17 @@ int mobius_accel_solve(dwf_ctx* ctx, const dwf_params* target, const dwf_params*
 int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U_natural, const void* phi, void* F, double* S,
                   double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
 
-/* Set / query the launch configuration of the hop kernels (sites per block and
- * s-values per thread); used by the autotuner.  kernel_id 0 = hop.  A zero
- * config restores the built-in default. */
-int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_block, int s_per_thread);
-int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* sites_per_block, int* s_per_thread);
+/* Set / query the launch configuration of the hop kernels for one (precision,
+ * Ls): 4D sites per workgroup, s-slices per thread, whether workgroups are
+ * remapped so that each XCD walks a contiguous range of the lattice, and
+ * whether the workgroup's links are staged in LDS.  Used by the autotuner;
+ * kernel_id 0 = hop.  sites_per_block = s_per_thread = 0 restores the default.
+ * Rejects shapes the kernel cannot run (more than 256 threads, Ls not divisible
+ * by s_per_thread, LDS above 64 KiB) with DWF_ERR_ARG. */
+int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_block, int s_per_thread,
+                 int xcd_remap, int link_lds);
+int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* sites_per_block, int* s_per_thread,
+                 int* xcd_remap, int* link_lds);
 
 #ifdef __cplusplus
 }

@@ -81,8 +81,8 @@ SIGNATURES = {
     "cg_ne_batched": ([_vp, _ci, _PP, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(SolveInfo)], _ci),
     "mobius_accel_solve": ([_vp, _PP, _PP, _vp, _vp, _vp, ctypes.POINTER(MadwfInfo)], _ci),
     "fermion_force": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(_cd), _cd, _ci, _vp, ctypes.POINTER(SolveInfo)], _ci),
-    "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci], _ci),
-    "dwf_tune_get": ([_vp, _ci, _ci, _ci, ctypes.POINTER(_ci), ctypes.POINTER(_ci)], _ci),
+    "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci, _ci, _ci], _ci),
+    "dwf_tune_get": ([_vp, _ci, _ci, _ci] + [ctypes.POINTER(_ci)] * 4, _ci),
 }
 
 
@@ -228,14 +228,15 @@ def fermion_force(ctx, p, U_natural, phi, F, tau_fg=0.0, out_kind=0, x_io=None, 
     return d
 
 
-def dwf_tune_set(ctx, prec, Ls, sites_per_block, s_per_thread, kernel_id=0):
-    _check(lib().dwf_tune_set(ctx.handle, int(kernel_id), int(prec), int(Ls), int(sites_per_block), int(s_per_thread)))
+def dwf_tune_set(ctx, prec, Ls, sites_per_block, s_per_thread, xcd_remap=1, link_lds=1, kernel_id=0):
+    _check(lib().dwf_tune_set(ctx.handle, int(kernel_id), int(prec), int(Ls), int(sites_per_block),
+                              int(s_per_thread), int(xcd_remap), int(link_lds)))
 
 
 def dwf_tune_get(ctx, prec, Ls, kernel_id=0):
-    a, b = _ci(0), _ci(0)
-    _check(lib().dwf_tune_get(ctx.handle, int(kernel_id), int(prec), int(Ls), ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+    v = [_ci(0) for _ in range(4)]
+    _check(lib().dwf_tune_get(ctx.handle, int(kernel_id), int(prec), int(Ls), *[ctypes.byref(t) for t in v]))
+    return tuple(t.value for t in v)
 
 
 from .fields import Lattice  # noqa: E402,F401

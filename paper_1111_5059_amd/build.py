@@ -22,15 +22,27 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 
 
+# the hop kernels are compiled once per compile-time fifth-dimension extent
+HOP_LS = (0, 8, 12, 16, 32)
+
+
 def sources():
-    return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    units = []
+    for f in sorted(os.listdir(CSRC)):
+        if not f.endswith((".hip", ".cpp")):
+            continue
+        if f.startswith("hop_"):
+            units += [(f, f"-DDWF_HOP_LS={ls}") for ls in HOP_LS]
+        units.append((f, None))
+    return units
 
 
-def _compile(src):
-    obj = os.path.join(OBJ, src + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".cpp"):
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit):
+    src, define = unit
+    tag = "" if define is None else "." + define.split("=")[1]
+    obj = os.path.join(OBJ, src + tag + ".o")
+    extra = [] if define is None else [define]
+    cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, obj, r.returncode, r.stdout + r.stderr
 

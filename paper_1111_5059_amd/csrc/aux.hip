@@ -122,9 +122,15 @@ __global__ void __launch_bounds__(256) axpby_kernel(double a, CHalf<P> x, double
   const int s = int(i - xs * Ls);
   cx<R> u[12], v[12];
   load_spinor<P>(x, xs, s, Ls, u);
-  load_spinor<P>(CHalf<P>{y.data, y.norm}, xs, s, Ls, v);
+  if (b != 0.0) {
+    load_spinor<P>(CHalf<P>{y.data, y.norm}, xs, s, Ls, v);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) v[k] = R(a) * u[k] + R(b) * v[k];
+    for (int k = 0; k < 12; ++k) v[k] = R(a) * u[k] + R(b) * v[k];
+  } else {
+    // y is not read: its previous contents may be uninitialised (0 * NaN = NaN)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = R(a) * u[k];
+  }
   store_spinor<P>(y, xs, s, Ls, v);
 }
 
@@ -211,11 +217,16 @@ __global__ void __launch_bounds__(256) cg_pupdate_kernel(CHalf<P> r, Half<P> p, 
   const int s = int(i - xs * Ls);
   cx<R> rv[12], pv[12];
   load_spinor<P>(r, xs, s, Ls, rv);
-  load_spinor<P>(CHalf<P>{p.data, p.norm}, xs, s, Ls, pv);
+  if (beta != 0.0) {
+    load_spinor<P>(CHalf<P>{p.data, p.norm}, xs, s, Ls, pv);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    pv[k].re = R(double(rv[k].re) + beta * double(pv[k].re));
-    pv[k].im = R(double(rv[k].im) + beta * double(pv[k].im));
+    for (int k = 0; k < 12; ++k) {
+      pv[k].re = R(double(rv[k].re) + beta * double(pv[k].re));
+      pv[k].im = R(double(rv[k].im) + beta * double(pv[k].im));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pv[k] = rv[k];
   }
   store_spinor<P>(p, xs, s, Ls, pv);
 }

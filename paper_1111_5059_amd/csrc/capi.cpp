@@ -386,7 +386,7 @@ int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* 
   return guarded([&]() { return dwf::fermion_force(ctx, *p, U, phi, F, S, tau_fg, out_kind, x_io, info); });
 }
 
-int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns) {
+int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns, int xcd, int ll) {
   if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
   if (kernel_id != 0 || prec < 0 || prec > 3 || Ls < 2 || Ls > 128) return fail(DWF_ERR_ARG, "bad tune key");
   const long long key = (long long)prec * 100000 + Ls;
@@ -398,21 +398,26 @@ int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns)
   if (Ls % ns != 0) return fail(DWF_ERR_ARG, "Ls must be divisible by s_per_thread");
   if (spb < 1 || spb * (Ls / ns) > 256) return fail(DWF_ERR_ARG, "sites_per_block * Ls / s_per_thread must be <= 256");
   const size_t elem = prec == DWF_FP64 ? 16 : 8;
-  if (size_t(spb) * 12 * Ls * elem > 65536) return fail(DWF_ERR_ARG, "epilogue LDS exceeds 64 KiB");
+  const size_t lelem = prec == DWF_FP64 ? 16 : prec == DWF_FP32 ? 8 : 4;
+  if (size_t(spb) * 12 * Ls * elem + (ll ? size_t(spb) * 72 * lelem : 0) > 65536)
+    return fail(DWF_ERR_ARG, "workgroup LDS (epilogue + staged links) exceeds 64 KiB");
   LaunchCfg c;
   c.spb = spb;
   c.ns = ns;
-  c.xcd = 1;
+  c.xcd = xcd ? 1 : 0;
+  c.ll = ll ? 1 : 0;
   ctx->tune[key] = c;
   return DWF_OK;
 }
 
-int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* spb, int* ns) {
-  if (!ctx || !spb || !ns) return fail(DWF_ERR_ARG, "NULL pointer");
+int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* spb, int* ns, int* xcd, int* ll) {
+  if (!ctx || !spb || !ns || !xcd || !ll) return fail(DWF_ERR_ARG, "NULL pointer");
   if (kernel_id != 0 || prec < 0 || prec > 3 || Ls < 2) return fail(DWF_ERR_ARG, "bad tune key");
   LaunchCfg c = hop_config(ctx, prec, Ls);
   *spb = c.spb;
   *ns = c.ns;
+  *xcd = c.xcd;
+  *ll = c.ll;
   return DWF_OK;
 }
 

@@ -50,6 +50,14 @@ const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
   g->nsites = g->V / 2;
   if (4 * g->V * 2 >= (1L << 31)) throw Error{DWF_ERR_ARG, "lattice too large for 32-bit link codes"};
   const long ns = g->nsites;
+  // tile extents: the largest of 8, 6, 4, 2 dividing each spatial extent, shrunk until a
+  // t-slice of a tile holds at most 128 sites of one parity
+  auto pick = [](int L) { for (int c : {8, 6, 4, 2}) if (L % c == 0) return c; return L; };
+  g->tile[0] = pick(X); g->tile[1] = pick(Y); g->tile[2] = pick(Z);
+  for (int k = 2; g->tile[0] * g->tile[1] * g->tile[2] > 256 && k >= 0; --k) {
+    int& t = g->tile[k];
+    for (int c : {4, 2}) if (c < t && (k == 0 ? X : k == 1 ? Y : Z) % c == 0) { t = c; break; }
+  }
   std::vector<int> site(ns), nbr(ns * 8), lsrc(ns * 8);
   auto idx = [&](int x, int y, int z, int t) { return long(x) + X * (long(y) + Y * (long(z) + long(Z) * t)); };
   for (int p = 0; p < 2; ++p) {
@@ -79,6 +87,23 @@ const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
         lsrc[xc * 8 + 4 + mu] = int(2 * (long(mu) * g->V + jb) + phb);
       }
     }
+    // Tiled traversal order of the output sites: 3D tiles of (tx, ty, tz) sites walked
+    // along t, tile after tile.  All 8 users of an input spinor are then processed
+    // within a few t-slices of one tile, a window that stays in one XCD's L2.
+    std::vector<int> order;
+    order.reserve(ns);
+    const int tx = g->tile[0], ty = g->tile[1], tz = g->tile[2];
+    for (int z0 = 0; z0 < Z; z0 += tz)
+      for (int y0 = 0; y0 < Y; y0 += ty)
+        for (int x0 = 0; x0 < X; x0 += tx)
+          for (int t = 0; t < T; ++t)
+            for (int z = z0; z < z0 + tz; ++z)
+              for (int y = y0; y < y0 + ty; ++y)
+                for (int x = x0; x < x0 + tx; ++x)
+                  if (((x + y + z + t) & 1) == p) order.push_back(int(idx(x, y, z, t) / 2));
+    if ((long)order.size() != ns) throw Error{DWF_ERR_ARG, "internal: traversal order incomplete"};
+    DWF_CHECK_HIP(hipMalloc(&g->d_order[p], ns * sizeof(int)));
+    DWF_CHECK_HIP(hipMemcpy(g->d_order[p], order.data(), ns * sizeof(int), hipMemcpyHostToDevice));
     DWF_CHECK_HIP(hipMalloc(&g->d_site[p], ns * sizeof(int)));
     DWF_CHECK_HIP(hipMalloc(&g->d_nbr[p], ns * 8 * sizeof(int)));
     DWF_CHECK_HIP(hipMalloc(&g->d_linksrc[p], ns * 8 * sizeof(int)));
@@ -96,10 +121,14 @@ LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls) {
   LaunchCfg c;
   c.ns = 1;
   c.xcd = 1;
+  c.ll = 1;
   int spb = 256 / Ls;
   if (spb < 1) spb = 1;
   while (spb > 1 && (spb * Ls) % 64 != 0) --spb;
   if ((spb * Ls) % 64 != 0) spb = 256 / Ls > 0 ? 256 / Ls : 1;
+  // the workgroup's LDS (epilogue staging + staged links) must fit in 64 KiB
+  const size_t per_site = size_t(12) * Ls * (prec == 0 ? 16 : 8) + 72 * (prec == 0 ? 16 : prec == 1 ? 8 : 4);
+  while (spb > 1 && spb * per_site > 65536) spb /= 2;
   c.spb = spb;
   return c;
 }

@@ -35,6 +35,14 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// dynamic LDS of one hop workgroup: epilogue staging + staged links
+template <typename P>
+inline size_t hop_lds_bytes(const LaunchCfg& cfg, int Ls, bool epi) {
+  size_t b = epi ? size_t(cfg.spb) * 12 * Ls * sizeof(cx<typename P::R>) : 0;
+  if (cfg.ll) b += size_t(cfg.spb) * 72 * sizeof(typename P::S);
+  return b;
+}
+
 template <typename P, bool PRO>
 __device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, cx<typename P::R> psi[12]) {
   using R = typename P::R;
@@ -58,8 +66,8 @@ __device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, c
 
 // One of the 8 hop directions: D = 0..3 forward (x+mu), 4..7 backward (x-mu).
 // H uses (1 - g_mu) forward and (1 + g_mu) backward; H^dag the opposite.
-template <int D, bool DAG, bool PRO, int NS, typename P>
-__device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, const typename P::S* L, int s0, int tps,
+template <int D, bool DAG, bool PRO, int NS, typename P, typename LPtr>
+__device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, LPtr L, int s0, int tps,
                                         cx<typename P::R> (&acc)[NS][12]) {
   using R = typename P::R;
   constexpr int MU = D & 3;
@@ -79,33 +87,57 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, cons
   }
 }
 
-template <typename P, int NS, bool DAG, bool PRO, bool EPI>
+template <typename P, int LS, int NS, bool DAG, bool PRO, bool EPI, bool LL>
 __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
-  const int Ls = a.Ls, tps = Ls / NS;
+  // LS > 0: the fifth-dimension extent is a compile-time constant (immediate load offsets)
+  const int Ls = LS > 0 ? LS : a.Ls, tps = Ls / NS;
+  HopArgs<P> ak = a;
+  ak.Ls = Ls;
   const long bid = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
   const int lsite = threadIdx.x / tps;
   const int s0 = threadIdx.x - lsite * tps;
-  const long x = bid * spb + lsite;
-  const bool active = (lsite < spb) && (x < a.nsites);
+  const long slot = bid * spb + lsite;
+  const bool active = (lsite < spb) && (slot < a.nsites);
+  const long x = active ? (a.order ? long(a.order[slot]) : slot) : 0;
   cx<R> acc[NS][12];
 #pragma unroll
   for (int j = 0; j < NS; ++j)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[j][k] = {R(0), R(0)};
+  using S = typename P::S;
+  const S* L;
+  if constexpr (LL) {
+    // Stage the 8 links of each of the workgroup's sites in LDS with coalesced loads
+    // (one read per element instead of one per s-slice lane); lanes then read them
+    // through the LDS pipe, which leaves the texture-data path to the spinors.
+    S* llds = reinterpret_cast<S*>(smem_raw + (EPI ? size_t(spb) * 12 * Ls * sizeof(cx<R>) : 0));
+    const long base = bid * spb;
+    for (int i = threadIdx.x; i < spb * 72; i += blockDim.x) {
+      const int ls = i / 72;
+      const long sl = base + ls;
+      if (sl < a.nsites) {
+        const long xs = a.order ? long(a.order[sl]) : sl;
+        llds[i] = a.links[xs * 72 + (i - ls * 72)];
+      }
+    }
+    __syncthreads();
+    L = llds + lsite * 72;
+  } else {
+    L = a.links + x * 72;
+  }
   if (active) {
     const int* nb = a.nbr + x * 8;
-    const typename P::S* L = a.links + x * 72;
-    hop_dir<0, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<1, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<2, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<3, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<4, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<5, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<6, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
-    hop_dir<7, DAG, PRO, NS>(a, nb, L, s0, tps, acc);
+    hop_dir<0, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<1, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<2, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<3, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<4, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<5, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<6, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<7, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
   }
 #pragma unroll
   for (int j = 0; j < NS; ++j)
@@ -175,28 +207,45 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
   }
 }
 
-template <typename P, int NS, bool DAG, bool PRO, bool EPI>
+template <typename P, int LS, int NS, bool DAG, bool PRO, bool EPI>
 static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
-  using R = typename P::R;
   const int tps = a.Ls / NS;
   const int threads = cfg.spb * tps;
   const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
-  const size_t lds = EPI ? size_t(cfg.spb) * 12 * a.Ls * sizeof(cx<R>) : 0;
-  hipLaunchKernelGGL((hop_kernel<P, NS, DAG, PRO, EPI>), dim3((unsigned)blocks), dim3(threads), lds, st, a, cfg.spb,
-                     cfg.xcd);
+  const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, EPI);
+  if (cfg.ll)
+    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
+                       cfg.spb, cfg.xcd);
+  else
+    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, false>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
+                       cfg.spb, cfg.xcd);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template <typename P, int NS>
+template <typename P, int LS, int NS>
 static int launch_hop_ns(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
   const bool epi = a.E != nullptr;
   if (dag) {
-    return epi ? launch_hop_t<P, NS, true, false, true>(a, cfg, st) : launch_hop_t<P, NS, true, false, false>(a, cfg, st);
+    return epi ? launch_hop_t<P, LS, NS, true, false, true>(a, cfg, st)
+               : launch_hop_t<P, LS, NS, true, false, false>(a, cfg, st);
   }
   if (pro) {
-    return epi ? launch_hop_t<P, NS, false, true, true>(a, cfg, st) : launch_hop_t<P, NS, false, true, false>(a, cfg, st);
+    return epi ? launch_hop_t<P, LS, NS, false, true, true>(a, cfg, st)
+               : launch_hop_t<P, LS, NS, false, true, false>(a, cfg, st);
   }
-  return epi ? launch_hop_t<P, NS, false, false, true>(a, cfg, st) : launch_hop_t<P, NS, false, false, false>(a, cfg, st);
+  return epi ? launch_hop_t<P, LS, NS, false, false, true>(a, cfg, st)
+             : launch_hop_t<P, LS, NS, false, false, false>(a, cfg, st);
+}
+
+// One compile-time fifth-dimension extent (0: runtime extent).  Each (precision, LS)
+// pair is instantiated in its own translation unit (see the build script).
+template <typename P, int LS>
+int launch_hop_ls(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
+  switch (cfg.ns) {
+    case 1: return launch_hop_ns<P, LS, 1>(a, dag, pro, cfg, st);
+    case 2: return launch_hop_ns<P, LS, 2>(a, dag, pro, cfg, st);
+    default: return launch_hop_ns<P, LS, 4>(a, dag, pro, cfg, st);
+  }
 }
 
 // Validates the launch shape against the kernel's assumptions before launching:
@@ -209,12 +258,15 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
   if (dagger && prologue) return -1;
   const int threads = cfg.spb * (a.Ls / cfg.ns);
   if (threads > 256) return -1;
-  if (a.E && size_t(cfg.spb) * 12 * a.Ls * sizeof(cx<R>) > 65536) return -1;
+  if (hop_lds_bytes<P>(cfg, a.Ls, a.E != nullptr) > 65536) return -1;
   if (a.nsites <= 0) return 0;
-  switch (cfg.ns) {
-    case 1: return launch_hop_ns<P, 1>(a, dagger, prologue, cfg, st);
-    case 2: return launch_hop_ns<P, 2>(a, dagger, prologue, cfg, st);
-    default: return launch_hop_ns<P, 4>(a, dagger, prologue, cfg, st);
+  // common extents get a compile-time Ls; the others run the generic kernel
+  switch (a.Ls) {
+    case 8: return launch_hop_ls<P, 8>(a, dagger, prologue, cfg, st);
+    case 12: return launch_hop_ls<P, 12>(a, dagger, prologue, cfg, st);
+    case 16: return launch_hop_ls<P, 16>(a, dagger, prologue, cfg, st);
+    case 32: return launch_hop_ls<P, 32>(a, dagger, prologue, cfg, st);
+    default: return launch_hop_ls<P, 0>(a, dagger, prologue, cfg, st);
   }
 }
 
@@ -303,7 +355,13 @@ inline long fifth_blocks(long nsites, int Ls, size_t elem) {
 
 }  // namespace dwf
 
+#define DWF_HOP_LS_ONE(P, L) \
+  template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);
+#define DWF_HOP_LS_EXTERN(P, L) \
+  extern template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);
 #define DWF_INSTANTIATE_HOP(P)                                                                                   \
+  DWF_HOP_LS_EXTERN(P, 0) DWF_HOP_LS_EXTERN(P, 8) DWF_HOP_LS_EXTERN(P, 12) DWF_HOP_LS_EXTERN(P, 16)               \
+  DWF_HOP_LS_EXTERN(P, 32)                                                                                      \
   template int dwf::launch_hop<P>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);                \
   template int dwf::launch_fifth<P>(CHalf<P>, Half<P>, const P::R*, CHalf<P>, P::R, long, int, double*,         \
                                     hipStream_t);

@@ -18,6 +18,7 @@ struct HopArgs {
   Half<P> out;
   const typename P::S* links;  // [nsites][8][9] for the output parity
   const int* nbr;              // [nsites][8] neighbour x_cb in the input half
+  const int* order;            // [nsites] traversal order of the output sites (nullptr: x_cb order)
   long nsites;
   int Ls;
   typename P::R scale;
@@ -32,6 +33,7 @@ struct LaunchCfg {
   int spb;  // 4D sites per block
   int ns;   // s-values per thread
   int xcd;  // XCD-aware block order
+  int ll;   // links staged in LDS
 };
 
 template <typename P>
@@ -83,6 +85,7 @@ int launch_set_scalar(double* scalars, int slot, double v, hipStream_t st);
 // ---------------------------------------------------------------- packing
 struct GeomTables {
   const int* site[2];    // [nsites] lexicographic index of x_cb, per parity
+  const int* order[2];   // [nsites] tiled traversal order of the x_cb of each parity
   const int* nbr[2];     // [nsites][8] neighbour x_cb (other parity) for output parity p
   const int* linksrc[2]; // [nsites][8] (mu*V + i) of the link used, sign bit = boundary phase -1
   long V, nsites;

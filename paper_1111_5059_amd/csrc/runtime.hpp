@@ -41,12 +41,15 @@ struct Geometry {
   int* d_site[2] = {nullptr, nullptr};
   int* d_nbr[2] = {nullptr, nullptr};
   int* d_linksrc[2] = {nullptr, nullptr};
+  int* d_order[2] = {nullptr, nullptr};
+  int tile[3] = {0, 0, 0};
   GeomTables tables() const {
     GeomTables t;
     for (int p = 0; p < 2; ++p) {
       t.site[p] = d_site[p];
       t.nbr[p] = d_nbr[p];
       t.linksrc[p] = d_linksrc[p];
+      t.order[p] = d_order[p];
     }
     t.V = V;
     t.nsites = nsites;
@@ -57,6 +60,7 @@ struct Geometry {
       if (d_site[p]) (void)hipFree(d_site[p]);
       if (d_nbr[p]) (void)hipFree(d_nbr[p]);
       if (d_linksrc[p]) (void)hipFree(d_linksrc[p]);
+      if (d_order[p]) (void)hipFree(d_order[p]);
     }
   }
 };
@@ -134,6 +138,7 @@ struct Op {
     a.out = out;
     a.links = U[out_par];
     a.nbr = g->d_nbr[out_par];
+    a.order = g->d_order[out_par];
     a.nsites = g->nsites;
     a.Ls = Ls;
     a.scale = R(scale);

@@ -108,7 +108,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   // p = r
   DWF_CHECK_LAUNCH(launch_axpby<Pi>(1.0, cv(r), 0.0, p, n5, Ls, s));
   DWF_CHECK_LAUNCH(launch_set_scalar(sc, S_RR, rr, s));
-  double rr_max = rr;
+  double rr_max = rr, rr_true = rr;
   const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
   const int nb_red = reduction_blocks(n5);
   int it = 0;
@@ -122,14 +122,19 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
     double rr_new = read_scalar(ctx, sc, S_RRNEW);
     ++it;
     if (!std::isfinite(rr_new)) throw Error{DWF_ERR_NAN, "non-finite residual in CG iteration"};
-    if (MIXED && (rr_new < delta * delta * rr_max || rr_new <= target)) {
+    // reliable update when the iterated residual has dropped by delta since the last one,
+    // when it claims convergence, or when it has grown 100x above the last true residual
+    // (a diverging low-precision recurrence)
+    const bool diverging = rr_new > 1e4 * rr_true;
+    if (MIXED && (rr_new < delta * delta * rr_max || rr_new <= target || diverging)) {
       // reliable update: fold the FP32 increment into the FP64 solution, recompute r in FP64
       DWF_CHECK_LAUNCH(launch_accumulate<PX>(x, xl, n5, Ls, s));
       rr_new = true_residual();
       DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
       rr_max = rr_new;
+      rr_true = rr_new;
       st->reliable_updates++;
-      if (rr_new > target && RESTART) {
+      if (rr_new > target && (RESTART || diverging)) {
         // BF16 (8-bit mantissa): the retained direction loses conjugacy and CG stagnates;
         // restart the Krylov space from the recomputed residual.
         DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, 0.0, sc, rr_new, n5, Ls, s));
