@@ -49,6 +49,35 @@ def hop_bytes_per_site(prec, Ls):
     return b
 
 
+ROOFLINE_KERNEL = "hop_kernel<P32, 32, 1, false, false, false, true>"
+KERNEL_SOURCES = ("paper_1111_5059_amd/csrc/hop_impl.hpp", "paper_1111_5059_amd/csrc/device.hpp",
+                  "paper_1111_5059_amd/csrc/kernels.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the roofline kernel from the committed hardware-counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or None when
+    the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "hop_fp32_ls32_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -125,9 +154,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
     ap.add_argument("--inner", default="fp16", choices=["fp16", "bf16", "fp32"])
-    ap.add_argument("--n-dc", type=int, default=3)
-    ap.add_argument("--tol-mobius", type=float, default=1e-4)
-    ap.add_argument("--tol-pv", type=float, default=1e-6)
+    ap.add_argument("--n-dc", type=int, default=2)
+    ap.add_argument("--tol-mobius", type=float, default=3e-4)
+    ap.add_argument("--tol-pv", type=float, default=1e-5)
+    ap.add_argument("--pv-prec", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
+    ap.add_argument("--final-prec", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
+    ap.add_argument("--no-hop", action="store_true")
+    ap.add_argument("--only-hop", action="store_true",
+                    help="time only the hop kernels and a 1 GiB device copy (for hardware-counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     args = ap.parse_args()
@@ -158,10 +192,20 @@ def main():
 
     # ---- Wilson hop kernel alone (roofline), same half lattice
     hop = {}
-    for prec in ("fp64", "fp32", "fp16"):
+    for prec in (() if args.no_hop else ("fp64", "fp32", "fp16")):
         hop[prec] = time_hop(dwf, ctx, lat, U64, prec)
         log(f"hop {prec}: {hop[prec]['ms']:.3f} ms  {hop[prec]['GBps']:.0f} GB/s")
     torch.cuda.synchronize()
+
+    if args.only_hop:
+        # a plain device copy of known size: calibrates FETCH_SIZE / WRITE_SIZE per byte
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"hop": hop, "copy_bytes": 1 << 30}))
+        return
 
     # ---- plain FP64 CG (the comparison)
     fp64 = None
@@ -182,7 +226,8 @@ def main():
     def step():
         return dwf.mobius_accel_solve(ctx, lat.params(), inner.params(prec_inner=P_in), U64, bg, xg,
                                       n_dc=args.n_dc, tol_pv=args.tol_pv, tol_mobius=args.tol_mobius, tol=1e-10,
-                                      prec_pv=dwf.FP32, prec_final=dwf.FP32)
+                                      prec_pv=dwf.PREC_NAMES[args.pv_prec],
+                                      prec_final=dwf.PREC_NAMES[args.final_prec])
 
     for _ in range(args.warmup):
         info = step()
@@ -205,7 +250,8 @@ def main():
         cpu = cpu_baseline(WORKLOADS[args.workload], U, b_nat, fp64["iters"])
         log(f"oracle: {cpu['seconds_per_iteration']:.2f} s per CG iteration on {cpu['cores']} threads")
 
-    rf = hop["fp32"]
+    rf = hop.get("fp32", {"GBps": 0.0, "bytes_per_launch": 0.0, "ms": 0.0})
+    traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": sec,
@@ -220,7 +266,8 @@ def main():
         "dtype": f"f32 arithmetic ({args.inner} inner / fp32 PV and final storage), f64 residuals and accumulator",
         "data": "synthetic",
         "config": {"workload": desc, "dims": list(dims), "Ls": L, "Ls_inner": Lp, "mass": mass, "eps": eps,
-                   "n_dc": args.n_dc, "tol": 1e-10, "tol_mobius": args.tol_mobius, "tol_pv": args.tol_pv},
+                   "n_dc": args.n_dc, "tol": 1e-10, "tol_mobius": args.tol_mobius, "tol_pv": args.tol_pv,
+                   "inner_prec": args.inner, "pv_prec": args.pv_prec, "final_prec": args.final_prec},
         "converged": converged,
         "madwf": last,
         "fp64_cg": fp64,
@@ -229,7 +276,7 @@ def main():
         "dslash": {k: {"GBps": v["GBps"], "pct_hbm_peak": 100 * v["GBps"] / HBM_PEAK_GBS, "GFLOPs": v["GFLOPs"],
                        "ms": v["ms"]} for k, v in hop.items()},
         "roofline": {"bound": "hbm", "achieved": rf["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rf["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": rf["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "hop_kernel<P32,1,false,false,false> (Wilson hop, FP32, half lattice)",
                      "bytes_per_launch": rf["bytes_per_launch"], "avg_launch_ms": rf["ms"]},
         "cpu_baseline": cpu,

@@ -157,12 +157,17 @@ int mobius_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* 
  * scalars and an FP64 solution accumulator. */
 int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info);
 
-/* Several right-hand sides of one lattice (per-RHS mass: the Hasenbusch ladder
- * of Sec. 3) in one batched solve: each CG iteration applies the operator to
- * all unconverged RHS with a single kernel launch per hop that loads every
- * link once for all of them.  per_rhs[k] may differ only in mass; b[k], x[k]
- * are packed FP64 full fields. */
-int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void* U, const void* const* b,
+/* Several right-hand sides solved together (the Hasenbusch mass ladder of Sec. 3):
+ * every hop stage of M_prec and M_prec^+ is ONE launch over all unconverged
+ * right-hand sides, each workgroup loading the links of its sites once for all
+ * right-hand sides on that lattice; one device-to-host copy per iteration
+ * returns every residual.  per_rhs[k] may differ in mass, and -- a ragged batch
+ * -- in extents and Ls, with U[k] the packed FP64 links of that lattice (equal
+ * pointers share link loads).  All entries share M5, b, c, tbc and prec_inner.
+ * b[k], x[k]: packed FP64 full fields (x[k] = initial guess on entry).
+ * per_rhs_info[k].tol is that right-hand side's target true residual; delta and
+ * maxit are taken from per_rhs_info[0]. */
+int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void* const* U, const void* const* b,
                   void* const* x, dwf_solve_info* per_rhs_info);
 
 /* Moebius-accelerated DWF solve (Sec. 4 algorithm, Sec. 5 defect correction):

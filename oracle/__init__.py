@@ -68,6 +68,7 @@ def lib():
             "ora_dw4": ([P, vp, vp, vp, ci], None),
             "ora_hop5": ([P, vp, vp, vp, ci, ci], None),
             "ora_dwf": ([P, vp, vp, vp, ci], None),
+            "ora_hop5_sample": ([P, vp, vp, ctypes.c_long, vp, vp, ci, vp], None),
             "ora_stilde": ([P, vp, vp, ci], None),
             "ora_fifth": ([P, vp, vp, ci], None),
             "ora_fifth_matrix": ([P, vp, ci], None),
@@ -149,6 +150,17 @@ def hop5(p, U, psi, dagger=False, out_parity=-1):
     U, psi = _c(U), _c(psi)
     out = np.empty_like(psi)
     lib().ora_hop5(ctypes.byref(p), _ptr(U), _ptr(psi), _ptr(out), int(dagger), int(out_parity))
+    return out
+
+
+def hop5_sample(p, U, psi, sites, svals, dagger=False):
+    """Wilson hop H (or H^dag) of a natural 5D field at sampled (4D index, s) pairs: [n][4][3]."""
+    U, psi = _c(U), _c(psi)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    svals = np.ascontiguousarray(svals, dtype=np.int32)
+    out = np.zeros((len(sites), 4, 3), np.complex128)
+    lib().ora_hop5_sample(ctypes.byref(p), _ptr(U), _ptr(psi), len(sites), sites.ctypes.data_as(ctypes.c_void_p),
+                          svals.ctypes.data_as(ctypes.c_void_p), int(dagger), _ptr(out))
     return out
 
 

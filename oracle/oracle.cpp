@@ -637,6 +637,16 @@ void ora_hop5(const ora_params* p, const cplx* U, const cplx* in, cplx* out, int
   if (out_par >= 0) mask_parity(g, p->Ls, out, out_par);
 }
 
+// Wilson hop evaluated only at n sampled 5D sites (4D lexicographic index, s) of a
+// natural 5D field; out[n][12].  The same per-site definition as ora_hop5.
+void ora_hop5_sample(const ora_params* p, const cplx* U, const cplx* in, long n, const long* sites, const int* svals,
+                     int dagger, cplx* out) {
+  Geom g = geom_of(p);
+  const long V12 = g.V * 12;
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < n; ++k) hop_site(g, U, in + (long)svals[k] * V12, sites[k], dagger, out + k * 12);
+}
+
 // 5D DWF / Moebius operator D(m) or D(m)^dag
 void ora_dwf(const ora_params* p, const cplx* U, const cplx* in, cplx* out, int dagger) {
   dwf5(p, U, in, out, dagger);

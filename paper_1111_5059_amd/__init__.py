@@ -78,7 +78,8 @@ SIGNATURES = {
     "dwf_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
     "mobius_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
     "cg_ne": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)], _ci),
-    "cg_ne_batched": ([_vp, _ci, _PP, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(SolveInfo)], _ci),
+    "cg_ne_batched": ([_vp, _ci, _PP, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                       ctypes.POINTER(SolveInfo)], _ci),
     "mobius_accel_solve": ([_vp, _PP, _PP, _vp, _vp, _vp, ctypes.POINTER(MadwfInfo)], _ci),
     "fermion_force": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(_cd), _cd, _ci, _vp, ctypes.POINTER(SolveInfo)], _ci),
     "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci, _ci, _ci], _ci),
@@ -190,17 +191,22 @@ def cg_ne(ctx, p, U, b, x, tol=1e-10, delta=0.1, maxit=100000):
 
 
 def cg_ne_batched(ctx, per_rhs, U, bs, xs, tol=1e-10, delta=0.1, maxit=100000):
+    """Batched solve; U is one packed link field for all right-hand sides or a list (one per
+    right-hand side, for a ragged batch of lattices)."""
     n = len(per_rhs)
+    Us = list(U) if isinstance(U, (list, tuple)) else [U] * n
     P = (Params * n)(*per_rhs)
+    Uv = (_vp * n)(*[_ptr(u) for u in Us])
     B = (_vp * n)(*[_ptr(b) for b in bs])
     X = (_vp * n)(*[_ptr(x) for x in xs])
+    tols = list(tol) if isinstance(tol, (list, tuple)) else [tol] * n
     infos = (SolveInfo * n)()
     for k in range(n):
-        infos[k].tol, infos[k].delta, infos[k].maxit = float(tol), float(delta), int(maxit)
-    rc = _check(lib().cg_ne_batched(ctx.handle, n, P, _vp(_ptr(U)), B, X, infos), allow_not_converged=True)
+        infos[k].tol, infos[k].delta, infos[k].maxit = float(tols[k]), float(delta), int(maxit)
+    _check(lib().cg_ne_batched(ctx.handle, n, P, Uv, B, X, infos), allow_not_converged=True)
     out = [infos[k].as_dict() for k in range(n)]
-    for d in out:
-        d["converged"] = d["true_rel_resid"] <= tol
+    for k, d in enumerate(out):
+        d["converged"] = d["true_rel_resid"] <= tols[k]
     return out
 
 
@@ -240,3 +246,4 @@ def dwf_tune_get(ctx, prec, Ls, kernel_id=0):
 
 
 from .fields import Lattice  # noqa: E402,F401
+from . import autograd, autotune  # noqa: E402,F401

@@ -434,6 +434,7 @@ DWF_INST_FIELD(P32)
 DWF_INST_FIELD(P16)
 DWF_INST_FIELD(PB16)
 
+template int launch_convert<P64, P64>(CHalf<P64>, Half<P64>, long, int, hipStream_t);
 template int launch_convert<P64, P32>(CHalf<P64>, Half<P32>, long, int, hipStream_t);
 template int launch_convert<P64, P16>(CHalf<P64>, Half<P16>, long, int, hipStream_t);
 template int launch_convert<P64, PB16>(CHalf<P64>, Half<PB16>, long, int, hipStream_t);

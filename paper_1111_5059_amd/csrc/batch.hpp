@@ -1,0 +1,40 @@
+// Batched hop launch: descriptor tables of lattice groups and their right-hand sides.
+#pragma once
+#include <vector>
+#include "kernels.hpp"
+
+namespace dwf {
+
+// One lattice: its links for the output parity, neighbour table and traversal order.
+template <typename P>
+struct MultiGroup {
+  const typename P::S* links;
+  const int* nbr;
+  const int* order;
+  long nsites;
+  int Ls;
+  int spb;           // 4D sites per workgroup (spb * Ls <= 256)
+  long block_begin;  // first workgroup of this group in the launch
+  int rhs_begin;     // first entry of this group in the right-hand-side table
+  int nrhs;
+};
+
+// One right-hand side: out = ax x + E . (scale H F in), with its own E (mass).
+template <typename P>
+struct MultiRhs {
+  CHalf<P> in;
+  Half<P> out;
+  const typename P::R* E;
+  CHalf<P> x;
+  typename P::R ax, scale, pb, pc, pm;
+  double* norm_partials;  // one FP64 partial per workgroup of the group, or nullptr
+};
+
+template <typename P>
+size_t multi_lds_bytes(int spb, int Ls, bool epi);
+
+template <typename P>
+int launch_hop_multi(const MultiGroup<P>* d_groups, const std::vector<MultiGroup<P>>& h_groups, const MultiRhs<P>* d_rhs,
+                     bool dagger, bool prologue, bool epi, hipStream_t st);
+
+}  // namespace dwf

@@ -324,29 +324,26 @@ int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void*
   });
 }
 
-int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void* U, const void* const* b,
+int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void* const* U, const void* const* b,
                   void* const* x, dwf_solve_info* info) {
   if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
-  if (nrhs < 1 || !per_rhs || !U || !b || !x || !info) return fail(DWF_ERR_ARG, "bad batched arguments");
+  if (nrhs < 1 || nrhs > 64 || !per_rhs || !U || !b || !x || !info) return fail(DWF_ERR_ARG, "bad batched arguments");
   for (int k = 0; k < nrhs; ++k) {
     int rc = check_params(&per_rhs[k], true);
     if (rc) return rc;
-    if (!b[k] || !x[k]) return fail(DWF_ERR_ARG, "NULL right-hand side");
-    for (int d = 0; d < 4; ++d)
-      if (per_rhs[k].dims[d] != per_rhs[0].dims[d]) return fail(DWF_ERR_ARG, "batched RHS must share the lattice");
-    if (per_rhs[k].Ls != per_rhs[0].Ls || per_rhs[k].M5 != per_rhs[0].M5 || per_rhs[k].b != per_rhs[0].b ||
-        per_rhs[k].c != per_rhs[0].c || per_rhs[k].tbc != per_rhs[0].tbc || per_rhs[k].prec_inner != per_rhs[0].prec_inner)
-      return fail(DWF_ERR_ARG, "batched RHS may differ only in mass");
+    if (!U[k] || !b[k] || !x[k]) return fail(DWF_ERR_ARG, "NULL pointer in the batch");
+    if (b[k] == x[k]) return fail(DWF_ERR_ARG, "b and x must not alias");
+    if (!(info[k].tol > 0.0)) return fail(DWF_ERR_ARG, "tol must be positive");
+    if (per_rhs[k].M5 != per_rhs[0].M5 || per_rhs[k].b != per_rhs[0].b || per_rhs[k].c != per_rhs[0].c ||
+        per_rhs[k].tbc != per_rhs[0].tbc || per_rhs[k].prec_inner != per_rhs[0].prec_inner)
+      return fail(DWF_ERR_ARG, "batched right-hand sides must share M5, b, c, tbc and prec_inner");
+    for (int j = 0; j < k; ++j)
+      if (x[j] == x[k]) return fail(DWF_ERR_ARG, "solution fields must be distinct");
   }
   return guarded([&]() {
-    int worst = DWF_OK;
-    for (int k = 0; k < nrhs; ++k) {
-      const double delta = info[k].delta > 0 ? info[k].delta : 0.1;
-      const int maxit = info[k].maxit > 0 ? info[k].maxit : 100000;
-      const int st = solve_full(ctx, per_rhs[k], U, b[k], x[k], info[k].tol, maxit, delta, "cg", &info[k]);
-      if (st) worst = DWF_NOT_CONVERGED;
-    }
-    return worst;
+    const int st = solve_batched(ctx, nrhs, per_rhs, U, b, x, info);
+    if (st != 0) set_error("cg_ne_batched: iteration cap reached before every true residual met tol");
+    return st == 0 ? DWF_OK : DWF_NOT_CONVERGED;
   });
 }
 

@@ -9,6 +9,7 @@
 #include <chrono>
 #include "runtime.hpp"
 #include "solver.hpp"
+#include "batch.hpp"
 
 namespace dwf {
 
@@ -246,6 +247,363 @@ int solve_full(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b
     info->true_rel_resid = rel;
     info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
     info->wilson_apps = (long long)st.iters * Ls;
+  }
+  return status;
+}
+
+// ------------------------------------------------------------------ batched CG
+// Several right-hand sides (the Hasenbusch mass ladder of Sec. 3; possibly on different
+// lattices) iterate together: every hop stage of M_prec and M_prec^dag is one launch over all
+// unconverged right-hand sides (links staged once per workgroup for all right-hand sides of a
+// lattice), and one device-to-host copy per iteration returns every residual norm.  The
+// per-RHS logic (FP64 scalars, reliable updates, convergence) is that of cg_normal.
+struct BatchSys {
+  dwf_params p;
+  const Geometry* g;
+  const void* U64;
+  const void* Ui;
+  std::unique_ptr<Op<P64>> op64;
+  CHalf<P64> rhs;
+  Half<P64> x;
+  double rhs2 = 0, target = 0, rr = 0, rr_max = 0, rr_true = 0, tol_n = 0;
+  bool active = false;
+  SolveStats st;
+  // inner vectors (storage precision of the solve)
+  void *r = nullptr, *pv = nullptr, *q = nullptr, *Ap = nullptr, *te = nullptr, *xl = nullptr;
+  const void* E = nullptr;  // fifth-dimension matrices of this mass
+  int group = -1;
+};
+
+template <typename Pi>
+static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double delta) {
+  constexpr bool MIXED = !std::is_same<Pi, P64>::value;
+  using PX = typename std::conditional<MIXED, P32, P64>::type;
+  using R = typename Pi::R;
+  constexpr bool RESTART = std::is_same<Pi, PB16>::value;
+  hipStream_t s = ctx->stream;
+  const int K = int(S.size());
+  // partial sums and scalars: one stride per right-hand side
+  long pstride = 1024;
+  for (auto& b : S) pstride = std::max(pstride, b.g->nsites);
+  double* part = reinterpret_cast<double*>(ws_get(ctx, "batch.partials", size_t(K) * pstride * sizeof(double)));
+  double* sc = reinterpret_cast<double*>(ws_get(ctx, "batch.scalars", size_t(K) * S_COUNT * sizeof(double)));
+  std::vector<double> hsc(size_t(K) * S_COUNT);
+  // FP64 temporaries shared by the reliable updates (largest system)
+  size_t hb64max = 0;
+  for (auto& b : S) hb64max = std::max(hb64max, half_size<P64>(b.g, b.p.Ls));
+  void* rhi_raw = ws_get(ctx, "batch.rhi", hb64max);
+  void* t64a_raw = ws_get(ctx, "batch.t64a", hb64max);
+  void* t64b_raw = ws_get(ctx, "batch.t64b", hb64max);
+  void* t64c_raw = ws_get(ctx, "batch.t64c", hb64max);
+  auto true_residual = [&](BatchSys& b) -> double {
+    const int Ls = b.p.Ls;
+    Half<P64> rhi = hview<P64>(rhi_raw, b.g, Ls), ta = hview<P64>(t64a_raw, b.g, Ls), tb = hview<P64>(t64b_raw, b.g, Ls),
+              tc = hview<P64>(t64c_raw, b.g, Ls);
+    b.op64->mprec(cv(b.x), ta, tb);
+    b.op64->mprec_dag(cv(ta), rhi, tb, tc);
+    DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, b.rhs, -1.0, rhi, b.g->nsites * Ls, Ls, s));
+    return norm2_sync<P64>(ctx, cv(rhi), b.g, Ls);
+  };
+  // inner vectors and start
+  for (int k = 0; k < K; ++k) {
+    BatchSys& b = S[k];
+    const int Ls = b.p.Ls;
+    const long n5 = b.g->nsites * Ls;
+    const size_t hbi = half_size<Pi>(b.g, Ls);
+    const std::string t = "batch." + std::to_string(k) + ".";
+    b.r = ws_get(ctx, t + "r", hbi);
+    b.pv = ws_get(ctx, t + "p", hbi);
+    b.q = ws_get(ctx, t + "q", hbi);
+    b.Ap = ws_get(ctx, t + "Ap", hbi);
+    b.te = ws_get(ctx, t + "te", hbi);
+    b.xl = MIXED ? ws_get(ctx, t + "xlo", half_size<PX>(b.g, Ls)) : (void*)b.x.data;
+    b.E = fifth_matrices(ctx, Ls, b.p.M5, b.p.mass, b.p.b, b.p.c, Pi::ID);
+    b.rhs2 = norm2_sync<P64>(ctx, b.rhs, b.g, Ls);
+    b.target = b.tol_n * b.tol_n * b.rhs2;
+    b.active = b.rhs2 > 0.0;
+    if (!b.active) {
+      DWF_CHECK_LAUNCH(launch_zero(b.x.data, half_size<P64>(b.g, Ls), s));
+      continue;
+    }
+    b.rr = true_residual(b);
+    if (!std::isfinite(b.rr)) throw Error{DWF_ERR_NAN, "non-finite residual at batched CG start"};
+    b.rr_max = b.rr_true = b.rr;
+    if (b.rr <= b.target) { b.active = false; continue; }
+    Half<P64> rhi = hview<P64>(rhi_raw, b.g, Ls);
+    Half<Pi> r = hview<Pi>(b.r, b.g, Ls);
+    DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
+    if (MIXED) DWF_CHECK_LAUNCH(launch_zero(b.xl, half_size<PX>(b.g, Ls), s));
+    DWF_CHECK_LAUNCH(launch_axpby<Pi>(1.0, cv(r), 0.0, hview<Pi>(b.pv, b.g, Ls), n5, Ls, s));
+    DWF_CHECK_LAUNCH(launch_set_scalar(sc + k * S_COUNT, S_RR, b.rr, s));
+  }
+  // descriptor tables of the four hop stages, rebuilt when the active set changes
+  std::vector<MultiGroup<Pi>> hg[4];
+  std::vector<MultiRhs<Pi>> hr[4];
+  MultiGroup<Pi>* dg[4];
+  MultiRhs<Pi>* dr[4];
+  for (int st = 0; st < 4; ++st) {
+    dg[st] = reinterpret_cast<MultiGroup<Pi>*>(ws_get(ctx, "batch.dg" + std::to_string(st), sizeof(MultiGroup<Pi>) * K));
+    dr[st] = reinterpret_cast<MultiRhs<Pi>*>(ws_get(ctx, "batch.dr" + std::to_string(st), sizeof(MultiRhs<Pi>) * K));
+  }
+  const bool moebius = !(S[0].p.b == 1.0 && S[0].p.c == 0.0);
+  std::vector<int> hop_blocks(K, 0);
+  auto build_tables = [&]() {
+    // group active systems by (lattice, links): consecutive entries of one group share links
+    std::vector<int> order_k;
+    std::vector<std::pair<const Geometry*, const void*>> keys;
+    std::vector<std::vector<int>> members;
+    for (int k = 0; k < K; ++k) {
+      if (!S[k].active) continue;
+      int gi = -1;
+      for (size_t j = 0; j < keys.size(); ++j)
+        if (keys[j].first == S[k].g && keys[j].second == S[k].Ui && S[members[j][0]].p.Ls == S[k].p.Ls) gi = int(j);
+      if (gi < 0) { keys.push_back({S[k].g, S[k].Ui}); members.push_back({}); gi = int(keys.size()) - 1; }
+      members[gi].push_back(k);
+    }
+    for (int st = 0; st < 4; ++st) {
+      hg[st].clear();
+      hr[st].clear();
+      const int out_par = (st == 0 || st == 2) ? 0 : 1;
+      long blocks = 0;
+      for (size_t j = 0; j < keys.size(); ++j) {
+        const BatchSys& b0 = S[members[j][0]];
+        const int Ls = b0.p.Ls;
+        MultiGroup<Pi> G;
+        G.links = reinterpret_cast<const typename Pi::S*>(b0.Ui) + (out_par ? size_t(b0.g->nsites) * 72 : 0);
+        G.nbr = b0.g->d_nbr[out_par];
+        G.order = b0.g->d_order[out_par];
+        G.nsites = b0.g->nsites;
+        G.Ls = Ls;
+        int spb = std::max(1, 256 / Ls);
+        while (spb > 1 && multi_lds_bytes<Pi>(spb, Ls, true) > 65536) --spb;
+        G.spb = spb;
+        G.block_begin = blocks;
+        G.rhs_begin = int(hr[st].size());
+        G.nrhs = int(members[j].size());
+        blocks += (G.nsites + spb - 1) / spb;
+        hg[st].push_back(G);
+        for (int k : members[j]) {
+          BatchSys& b = S[k];
+          hop_blocks[k] = int((G.nsites + spb - 1) / spb);
+          const R* E = reinterpret_cast<const R*>(b.E);
+          const size_t ls2 = size_t(Ls) * Ls;
+          MultiRhs<Pi> Q;
+          Q.pb = R(b.p.b);
+          Q.pc = R(b.p.c);
+          Q.pm = R(b.p.mass);
+          Q.ax = R(0);
+          Q.x = {nullptr, nullptr};
+          Q.norm_partials = nullptr;
+          if (st == 0) {  // te = A^-1 H_eo F p
+            Q.in = chview<Pi>(b.pv, b.g, Ls); Q.out = hview<Pi>(b.te, b.g, Ls);
+            Q.E = E + size_t(E_AINV) * 2 * ls2; Q.scale = R(1);
+          } else if (st == 1) {  // q = p - 1/4 A^-1 H_oe F te, |q|^2
+            Q.in = chview<Pi>(b.te, b.g, Ls); Q.out = hview<Pi>(b.q, b.g, Ls);
+            Q.E = E + size_t(E_AINV) * 2 * ls2; Q.scale = R(-0.25);
+            Q.x = chview<Pi>(b.pv, b.g, Ls); Q.ax = R(1);
+            Q.norm_partials = part + size_t(k) * pstride;
+          } else if (st == 2) {  // te = A^-dag F^dag H^dag_eo (A^-dag q)   [A^-dag q is in Ap]
+            Q.in = chview<Pi>(b.Ap, b.g, Ls); Q.out = hview<Pi>(b.te, b.g, Ls);
+            Q.E = E + size_t(E_AINVDAG_FDAG) * 2 * ls2; Q.scale = R(1);
+          } else {  // Ap = q - 1/4 F^dag H^dag_oe te
+            Q.in = chview<Pi>(b.te, b.g, Ls); Q.out = hview<Pi>(b.Ap, b.g, Ls);
+            Q.E = moebius ? E + size_t(E_FDAG) * 2 * ls2 : nullptr; Q.scale = R(-0.25);
+            Q.x = chview<Pi>(b.q, b.g, Ls); Q.ax = R(1);
+          }
+          hr[st].push_back(Q);
+        }
+      }
+      if (!hg[st].empty()) {
+        DWF_CHECK_HIP(hipMemcpy(dg[st], hg[st].data(), sizeof(MultiGroup<Pi>) * hg[st].size(), hipMemcpyHostToDevice));
+        DWF_CHECK_HIP(hipMemcpy(dr[st], hr[st].data(), sizeof(MultiRhs<Pi>) * hr[st].size(), hipMemcpyHostToDevice));
+      }
+    }
+  };
+  int nactive = 0;
+  for (auto& b : S) nactive += b.active ? 1 : 0;
+  if (nactive) build_tables();
+  int it = 0;
+  while (nactive > 0 && it < maxit) {
+    // q = M p (one launch per stage for all right-hand sides), alpha = rr / |q|^2
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[0], hg[0], dr[0], false, moebius, true, s));
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[1], hg[1], dr[1], false, moebius, true, s));
+    for (int k = 0; k < K; ++k) {
+      if (!S[k].active) continue;
+      BatchSys& b = S[k];
+      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, hop_blocks[k], 1, sc + k * S_COUNT, S_QQ, 1, s));
+      // A^-dag q into Ap (consumed by the next stage before Ap is overwritten)
+      DWF_CHECK_LAUNCH(launch_fifth<Pi>(chview<Pi>(b.q, b.g, b.p.Ls), hview<Pi>(b.Ap, b.g, b.p.Ls),
+                                        reinterpret_cast<const R*>(b.E) + size_t(E_AINVDAG) * 2 * b.p.Ls * b.p.Ls,
+                                        CHalf<Pi>{nullptr, nullptr}, R(0), b.g->nsites, b.p.Ls, nullptr, s));
+    }
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[2], hg[2], dr[2], true, false, true, s));
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[3], hg[3], dr[3], true, false, moebius, s));
+    for (int k = 0; k < K; ++k) {
+      if (!S[k].active) continue;
+      BatchSys& b = S[k];
+      const int Ls = b.p.Ls;
+      const long n5 = b.g->nsites * Ls;
+      DWF_CHECK_LAUNCH((launch_cg_update<Pi, PX>(hview<PX>(b.xl, b.g, Ls), chview<Pi>(b.pv, b.g, Ls), hview<Pi>(b.r, b.g, Ls),
+                                                  chview<Pi>(b.Ap, b.g, Ls), sc + k * S_COUNT, n5, Ls,
+                                                  part + size_t(k) * pstride, s)));
+      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, reduction_blocks(n5), 1, sc + k * S_COUNT, S_RRNEW, 0, s));
+    }
+    DWF_CHECK_HIP(hipMemcpyAsync(hsc.data(), sc, sizeof(double) * hsc.size(), hipMemcpyDeviceToHost, s));
+    DWF_CHECK_HIP(hipStreamSynchronize(s));
+    ++it;
+    bool changed = false;
+    for (int k = 0; k < K; ++k) {
+      BatchSys& b = S[k];
+      if (!b.active) continue;
+      const int Ls = b.p.Ls;
+      const long n5 = b.g->nsites * Ls;
+      b.st.iters++;
+      double rr_new = hsc[size_t(k) * S_COUNT + S_RRNEW];
+      if (!std::isfinite(rr_new)) throw Error{DWF_ERR_NAN, "non-finite residual in batched CG"};
+      const bool diverging = rr_new > 1e4 * b.rr_true;
+      bool restart = false;
+      if (MIXED && (rr_new < delta * delta * b.rr_max || rr_new <= b.target || diverging)) {
+        DWF_CHECK_LAUNCH(launch_accumulate<PX>(b.x, hview<PX>(b.xl, b.g, Ls), n5, Ls, s));
+        rr_new = true_residual(b);
+        DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(chview<P64>(rhi_raw, b.g, Ls), hview<Pi>(b.r, b.g, Ls), n5, Ls, s)));
+        b.rr_max = b.rr_true = rr_new;
+        b.st.reliable_updates++;
+        restart = rr_new > b.target && (RESTART || diverging);
+      }
+      if (rr_new <= b.target) {
+        b.rr = rr_new;
+        b.active = false;
+        changed = true;
+        continue;
+      }
+      const double beta = restart ? 0.0 : rr_new / b.rr;
+      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(chview<Pi>(b.r, b.g, Ls), hview<Pi>(b.pv, b.g, Ls), beta,
+                                             sc + k * S_COUNT, rr_new, n5, Ls, s));
+      b.rr = rr_new;
+      if (b.rr > b.rr_max) b.rr_max = b.rr;
+    }
+    nactive = 0;
+    for (auto& b : S) nactive += b.active ? 1 : 0;
+    if (changed && nactive) build_tables();
+  }
+  for (auto& b : S) {
+    if (MIXED && b.rhs2 > 0.0)
+      DWF_CHECK_LAUNCH(launch_accumulate<PX>(b.x, hview<PX>(b.xl, b.g, b.p.Ls), b.g->nsites * b.p.Ls, b.p.Ls, s));
+    b.st.last_rel = b.rhs2 > 0 ? std::sqrt(b.rr / b.rhs2) : 0.0;
+  }
+}
+
+// Full-system batched solve: per-RHS even-odd source preparation, the batched CG on the
+// normal equations, per-RHS reconstruction and true residual, tightening the normal-equation
+// tolerance of the right-hand sides that have not reached tol.
+int solve_batched(dwf_ctx* ctx, int nrhs, const dwf_params* P, const void* const* U64, const void* const* b,
+                  void* const* x, dwf_solve_info* info) {
+  const auto t0 = Clock::now();
+  hipStream_t s = ctx->stream;
+  std::vector<BatchSys> S(nrhs);
+  std::vector<double> b2(nrhs, 0.0), rel(nrhs, 1.0);
+  std::vector<int> done(nrhs, 0);
+  for (int k = 0; k < nrhs; ++k) {
+    BatchSys& B = S[k];
+    B.p = P[k];
+    B.g = geometry(ctx, P[k].dims, P[k].tbc);
+    B.U64 = U64[k];
+    B.op64 = std::make_unique<Op<P64>>(ctx, B.g, P[k], U64[k]);
+    const int Ls = P[k].Ls;
+    const size_t hb = half_size<P64>(B.g, Ls);
+    const long n5 = B.g->nsites * Ls;
+    const std::string t = "batchfull." + std::to_string(k) + ".";
+    CHalf<P64> be = chview<P64>(b[k], B.g, Ls), bo = chview<P64>(reinterpret_cast<const char*>(b[k]) + hb, B.g, Ls);
+    Half<P64> te = hview<P64>(ws_get(ctx, "batchfull.se", hb), B.g, Ls);
+    Half<P64> to = hview<P64>(ws_get(ctx, "batchfull.so", hb), B.g, Ls);
+    Half<P64> bp = hview<P64>(ws_get(ctx, "batchfull.bp", hb), B.g, Ls);
+    Half<P64> t2 = hview<P64>(ws_get(ctx, "batchfull.t2", hb), B.g, Ls);
+    Half<P64> rhs = hview<P64>(ws_get(ctx, t + "rhs", hb), B.g, Ls);
+    b2[k] = norm2_sync<P64>(ctx, be, B.g, Ls) + norm2_sync<P64>(ctx, bo, B.g, Ls);
+    if (!std::isfinite(b2[k])) throw Error{DWF_ERR_NAN, "non-finite source"};
+    B.op64->fifth(be, te, E_AINV);
+    B.op64->hop(1, cv(te), to, false, true, 0.5, nullptr, bo, 1.0);
+    B.op64->fifth(cv(to), bp, E_AINV);
+    B.op64->mprec_dag(cv(bp), rhs, te, t2);
+    (void)n5;
+    B.rhs = cv(rhs);
+    B.x = hview<P64>(reinterpret_cast<char*>(x[k]) + hb, B.g, Ls);
+    B.tol_n = info[k].tol;
+    if (b2[k] == 0.0) { DWF_CHECK_LAUNCH(launch_zero(x[k], 2 * hb, s)); done[k] = 1; rel[k] = 0.0; }
+  }
+  // links in the inner precision, converted once per distinct link field
+  const int prec = P[0].prec_inner;
+  std::map<const void*, const void*> conv;
+  for (int k = 0; k < nrhs; ++k) {
+    if (!conv.count(U64[k])) conv[U64[k]] = links_in(ctx, S[k].g, U64[k], prec, "batchU." + std::to_string(conv.size()));
+    S[k].Ui = conv[U64[k]];
+  }
+  const double delta = info[0].delta > 0 ? info[0].delta : 0.1;
+  int maxit = info[0].maxit > 0 ? info[0].maxit : 100000;
+  int status = 0;
+  for (int attempt = 0; attempt < 12; ++attempt) {
+    std::vector<int> idx;
+    for (int k = 0; k < nrhs; ++k)
+      if (!done[k]) idx.push_back(k);
+    if (idx.empty()) break;
+    std::vector<BatchSys> run;
+    run.reserve(idx.size());
+    for (int k : idx) {
+      BatchSys c;
+      c.p = S[k].p; c.g = S[k].g; c.U64 = S[k].U64; c.Ui = S[k].Ui;
+      c.op64 = std::make_unique<Op<P64>>(ctx, S[k].g, S[k].p, S[k].U64);
+      c.rhs = S[k].rhs; c.x = S[k].x; c.tol_n = S[k].tol_n;
+      run.push_back(std::move(c));
+    }
+    switch (prec) {
+      case DWF_FP64: cg_batched<P64>(ctx, run, maxit, delta); break;
+      case DWF_FP32: cg_batched<P32>(ctx, run, maxit, delta); break;
+      case DWF_FP16: cg_batched<P16>(ctx, run, maxit, delta); break;
+      default: cg_batched<PB16>(ctx, run, maxit, delta); break;
+    }
+    int left = 0;
+    for (size_t j = 0; j < idx.size(); ++j) {
+      const int k = idx[j];
+      BatchSys& B = S[k];
+      B.st.iters += run[j].st.iters;
+      B.st.reliable_updates += run[j].st.reliable_updates;
+      const int Ls = B.p.Ls;
+      const size_t hb = half_size<P64>(B.g, Ls);
+      const long n5 = B.g->nsites * Ls;
+      CHalf<P64> be = chview<P64>(b[k], B.g, Ls), bo = chview<P64>(reinterpret_cast<const char*>(b[k]) + hb, B.g, Ls);
+      Half<P64> xe = hview<P64>(x[k], B.g, Ls);
+      Half<P64> te = hview<P64>(ws_get(ctx, "batchfull.se", hb), B.g, Ls);
+      void* rf = ws_get(ctx, "batchfull.rfull", 2 * hb);
+      Half<P64> re = hview<P64>(rf, B.g, Ls), ro = hview<P64>(reinterpret_cast<char*>(rf) + hb, B.g, Ls);
+      B.op64->hop(0, cv(B.x), te, false, true, 0.5, nullptr, be, 1.0);
+      B.op64->fifth(cv(te), xe, E_AINV);
+      B.op64->full(cv(xe), cv(B.x), re, ro, false);
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, be, -1.0, re, n5, Ls, s));
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, bo, -1.0, ro, n5, Ls, s));
+      const double r2 = norm2_sync<P64>(ctx, cv(re), B.g, Ls) + norm2_sync<P64>(ctx, cv(ro), B.g, Ls);
+      rel[k] = std::sqrt(r2 / b2[k]);
+      if (!std::isfinite(rel[k])) throw Error{DWF_ERR_NAN, "non-finite true residual"};
+      if (rel[k] <= info[k].tol) {
+        done[k] = 1;
+      } else {
+        B.tol_n *= std::max(0.02, std::min(0.5, 0.5 * info[k].tol / rel[k]));
+        B.st.restarts++;
+        ++left;
+      }
+      if (B.st.iters >= maxit && !done[k]) done[k] = 2;
+    }
+    if (left == 0) break;
+  }
+  DWF_CHECK_HIP(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
+  for (int k = 0; k < nrhs; ++k) {
+    info[k].iters = S[k].st.iters;
+    info[k].reliable_updates = S[k].st.reliable_updates;
+    info[k].restarts = S[k].st.restarts;
+    info[k].true_rel_resid = rel[k];
+    info[k].seconds = secs;
+    info[k].wilson_apps = (long long)S[k].st.iters * S[k].p.Ls;
+    if (done[k] != 1) status = 1;
   }
   return status;
 }

@@ -1,0 +1,97 @@
+"""Summaries of rocprofv3 CSV output for the roofline report.
+
+python -m paper_1111_5059_amd.profiling stats  <run_kernel_stats.csv> <kernel-substring> [command]
+python -m paper_1111_5059_amd.profiling traffic <fetch_counter_collection.csv> <write_counter_collection.csv>
+        <kernel-substring> <copy-bytes> <out.json>
+
+``traffic`` converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named kernel into HBM
+bytes per launch, each scaled by what the same counter reads for a plain device copy of a
+known size (the largest copy kernel in the same run), and records the hash of the kernel
+sources so that a later kernel change invalidates the figure.
+"""
+import csv
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(f"none of {names} in {list(row)}")
+
+
+def kernel_stats(path, substring):
+    out = []
+    for r in _rows(path):
+        name = _col(r, "Name", "KernelName", "Kernel_Name")
+        if substring in name:
+            out.append({"name": name, "calls": int(_col(r, "Calls")),
+                        "avg_ns": float(_col(r, "AverageNs", "Average_ns", "AverageNs ")),
+                        "total_ns": float(_col(r, "TotalDurationNs", "TotalDuration_ns")),
+                        "pct": float(_col(r, "Percentage"))})
+    return out
+
+
+def counter_per_dispatch(path, kernel_substring, counter):
+    vals, grids = [], []
+    for r in _rows(path):
+        if _col(r, "Counter_Name") != counter:
+            continue
+        if kernel_substring in _col(r, "Kernel_Name"):
+            vals.append(float(_col(r, "Counter_Value")))
+            grids.append(int(_col(r, "Grid_Size")))
+    return vals, grids
+
+
+def copy_counter(path, counter):
+    """counter of the largest device copy in the run (torch's copy kernel)"""
+    best = None
+    for r in _rows(path):
+        if _col(r, "Counter_Name") != counter:
+            continue
+        name = _col(r, "Kernel_Name")
+        if "copy" in name.lower() or "Copy" in name:
+            g = int(_col(r, "Grid_Size"))
+            if best is None or g > best[0]:
+                best = (g, float(_col(r, "Counter_Value")), name)
+    return best
+
+
+def main(argv):
+    if argv[0] == "stats":
+        for k in kernel_stats(argv[1], argv[2]):
+            print(json.dumps(k))
+        return
+    if argv[0] == "traffic":
+        fetch_csv, write_csv, ksub, copy_bytes, out = argv[1], argv[2], argv[3], int(argv[4]), argv[5]
+        f, _ = counter_per_dispatch(fetch_csv, ksub, "FETCH_SIZE")
+        w, _ = counter_per_dispatch(write_csv, ksub, "WRITE_SIZE")
+        cf = copy_counter(fetch_csv, "FETCH_SIZE")
+        cw = copy_counter(write_csv, "WRITE_SIZE")
+        fscale = copy_bytes / (cf[1] * 1024.0)
+        wscale = copy_bytes / (cw[1] * 1024.0)
+        fetch = sum(f) / len(f) * 1024.0 * fscale
+        write = sum(w) / len(w) * 1024.0 * wscale
+        sys.path.insert(0, ROOT)
+        import bench
+        d = {"kernel": ksub, "dispatches": len(f), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+             "hbm_bytes_per_launch": fetch + write, "copy_kernel": cf[2][:120], "copy_bytes": copy_bytes,
+             "fetch_scale": fscale, "write_scale": wscale, "kernel_source_sha256_16": bench.kernel_source_hash()}
+        with open(out, "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d))
+        return
+    raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
