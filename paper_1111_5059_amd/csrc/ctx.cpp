@@ -169,6 +169,38 @@ static std::vector<double> transpose(const std::vector<double>& A, int n) {
   return T;
 }
 
+// The same operators in recurrence form (bidiagonal factor, then the inverse of a
+// bidiagonal).  Valid when |a| = |beta/alpha| <= 1, so that the scan's powers of a stay
+// bounded, and 1 + m a^Ls is not close to 0.
+bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, FifthScan<double>* out) {
+  const double d = 4.0 - M5, alpha = b * d + 1.0, beta = c * d - 1.0;
+  if (std::fabs(alpha) < 1e-14) return false;
+  const double a = -beta / alpha;
+  const double den = 1.0 + m * std::pow(a, Ls);
+  if (std::fabs(a) > 1.0 || std::fabs(den) < 1e-6) return false;
+  FifthScan<double> e{};
+  e.m = m;
+  for (int ch = 0; ch < 2; ++ch) {
+    FifthChir<double> q{};
+    const int dS = ch == 0 ? -1 : +1;  // direction S~ takes in this chirality; the adjoint takes -dS
+    q.a1 = 1.0; q.b1 = 0.0; q.d1 = dS; q.has_inv = 0; q.d2 = dS;
+    q.inv_alpha = 1.0 / alpha; q.a = a; q.corr = m / den;
+    switch (slot) {
+      case E_A: q.a1 = alpha; q.b1 = beta; q.d1 = dS; break;
+      case E_ADAG: q.a1 = alpha; q.b1 = beta; q.d1 = -dS; break;
+      case E_AINV: q.has_inv = 1; q.d2 = dS; break;
+      case E_AINVDAG: q.has_inv = 1; q.d2 = -dS; break;
+      case E_F: q.a1 = b; q.b1 = c; q.d1 = dS; break;
+      case E_FDAG: q.a1 = b; q.b1 = c; q.d1 = -dS; break;
+      case E_AINVDAG_FDAG: q.a1 = b; q.b1 = c; q.d1 = -dS; q.has_inv = 1; q.d2 = -dS; break;
+      default: return false;
+    }
+    e.ch[ch] = q;
+  }
+  *out = e;
+  return true;
+}
+
 const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec) {
   char key[256];
   snprintf(key, sizeof(key), "%d|%.17g|%.17g|%.17g|%.17g|%d", Ls, M5, m, b, c, prec == 0 ? 0 : 1);

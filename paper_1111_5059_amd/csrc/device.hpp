@@ -248,6 +248,109 @@ __device__ __forceinline__ void su3_mul_half(const cx<R> M[9], const cx<R> h[6],
     }
 }
 
+// ----------------------------------------------------------------- fifth-dimension operators along s
+// Each site-local operator of the even-odd DWF/Moebius system is, per chirality, a
+// bidiagonal factor (a1 + b1 S_d1) followed optionally by the inverse of another
+// bidiagonal (alpha + beta S_d2), where S_{-1} x_s = x_{s-1} (x_{-1} = -m x_{Ls-1}) and
+// S_{+1} x_s = x_{s+1} (x_{Ls} = -m x_0).  Chirality 0 = spins 0,1 (P+), 1 = spins 2,3 (P-).
+template <typename R>
+struct FifthChir {
+  R a1, b1;           // bidiagonal factor; b1 == 0: scalar
+  R inv_alpha, a;     // inverse of (alpha + beta S_d2): 1/alpha and a = -beta/alpha
+  R corr;             // m / (1 + m a^Ls)
+  int d1, d2;         // shift directions (-1 or +1)
+  int has_inv;
+};
+template <typename R>
+struct FifthScan {
+  FifthChir<R> ch[2];
+  R m;
+};
+
+// Apply the operator to the 12 components v[] held by this lane (slice s) when the Ls
+// lanes of a site are the consecutive lanes [seg*Ls, seg*Ls + Ls) of one wave.  The
+// inverse of (alpha + beta S_d) is the first-order recurrence y_s = u_s + a y_{s-+1},
+// u = w/alpha: a Hillis-Steele scan over the segment (log2 Ls shuffle steps) with zero
+// start, then the cyclic boundary y_{-1} = -m y_{Ls-1} (resp. y_{Ls} = -m y_0) is
+// restored in closed form:  y_s = P_s - m a^{s+1} P_{Ls-1} / (1 + m a^Ls)  (forward)
+// or y_s = Q_s - m a^{Ls-s} Q_0 / (1 + m a^Ls)  (backward).
+template <int LSEG, typename R>
+__device__ __forceinline__ R seg_shfl(R v, int src) {
+  return __shfl(v, src, LSEG);
+}
+
+template <int LSEG, typename R>
+__device__ __forceinline__ void fifth_scan_apply(cx<R> v[12], int s, const FifthScan<R>& e) {
+#pragma unroll
+  for (int ch = 0; ch < 2; ++ch) {
+    const FifthChir<R> c = e.ch[ch];
+    // bidiagonal factor
+    if (c.b1 != R(0)) {
+      const int src = (s + c.d1) & (LSEG - 1);
+      const bool wrap = (c.d1 < 0) ? (s == 0) : (s == LSEG - 1);
+      const R f = wrap ? -e.m * c.b1 : c.b1;
+#pragma unroll
+      for (int k = ch * 6; k < ch * 6 + 6; ++k) {
+        const R nr = seg_shfl<LSEG>(v[k].re, src), ni = seg_shfl<LSEG>(v[k].im, src);
+        v[k] = {c.a1 * v[k].re + f * nr, c.a1 * v[k].im + f * ni};
+      }
+    } else if (c.a1 != R(1)) {
+#pragma unroll
+      for (int k = ch * 6; k < ch * 6 + 6; ++k) v[k] = c.a1 * v[k];
+    }
+    if (!c.has_inv) continue;
+    // inverse of the bidiagonal (alpha + beta S_d2)
+#pragma unroll
+    for (int k = ch * 6; k < ch * 6 + 6; ++k) v[k] = c.inv_alpha * v[k];
+    R apow = c.a;
+    if (c.d2 < 0) {
+#pragma unroll
+      for (int off = 1; off < LSEG; off <<= 1) {
+#pragma unroll
+        for (int k = ch * 6; k < ch * 6 + 6; ++k) {
+          const R tr = __shfl_up(v[k].re, off, LSEG), ti = __shfl_up(v[k].im, off, LSEG);
+          if (s >= off) v[k] = {v[k].re + apow * tr, v[k].im + apow * ti};
+        }
+        apow *= apow;
+      }
+      // a^{s+1}
+      R as = R(1), base = c.a;
+      for (int e2 = s + 1; e2; e2 >>= 1) {
+        if (e2 & 1) as *= base;
+        base *= base;
+      }
+      const R w = -c.corr * as;
+#pragma unroll
+      for (int k = ch * 6; k < ch * 6 + 6; ++k) {
+        const R lr = seg_shfl<LSEG>(v[k].re, LSEG - 1), li = seg_shfl<LSEG>(v[k].im, LSEG - 1);
+        v[k] = {v[k].re + w * lr, v[k].im + w * li};
+      }
+    } else {
+#pragma unroll
+      for (int off = 1; off < LSEG; off <<= 1) {
+#pragma unroll
+        for (int k = ch * 6; k < ch * 6 + 6; ++k) {
+          const R tr = __shfl_down(v[k].re, off, LSEG), ti = __shfl_down(v[k].im, off, LSEG);
+          if (s + off < LSEG) v[k] = {v[k].re + apow * tr, v[k].im + apow * ti};
+        }
+        apow *= apow;
+      }
+      // a^{Ls-s}
+      R as = R(1), base = c.a;
+      for (int e2 = LSEG - s; e2; e2 >>= 1) {
+        if (e2 & 1) as *= base;
+        base *= base;
+      }
+      const R w = -c.corr * as;
+#pragma unroll
+      for (int k = ch * 6; k < ch * 6 + 6; ++k) {
+        const R fr = seg_shfl<LSEG>(v[k].re, 0), fi = seg_shfl<LSEG>(v[k].im, 0);
+        v[k] = {v[k].re + w * fr, v[k].im + w * fi};
+      }
+    }
+  }
+}
+
 // XCD-aware block order: the hardware deals workgroups round-robin over the 8
 // XCDs; remap so that each XCD walks one contiguous range of the lattice and
 // neighbouring sites share its L2.

@@ -87,7 +87,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, LPtr
   }
 }
 
-template <typename P, int LS, int NS, bool DAG, bool PRO, bool EPI, bool LL>
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL>
 __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
     // Stage the 8 links of each of the workgroup's sites in LDS with coalesced loads
     // (one read per element instead of one per s-slice lane); lanes then read them
     // through the LDS pipe, which leaves the texture-data path to the spinors.
-    S* llds = reinterpret_cast<S*>(smem_raw + (EPI ? size_t(spb) * 12 * Ls * sizeof(cx<R>) : 0));
+    S* llds = reinterpret_cast<S*>(smem_raw + (EPI == 1 ? size_t(spb) * 12 * Ls * sizeof(cx<R>) : 0));
     const long base = bid * spb;
     for (int i = threadIdx.x; i < spb * 72; i += blockDim.x) {
       const int ls = i / 72;
@@ -143,7 +143,12 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
   for (int j = 0; j < NS; ++j)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
-  if constexpr (EPI) {
+  if constexpr (EPI == 2) {
+    // recurrence form along s: the site's Ls lanes are one segment of the wave
+    static_assert(NS == 1 && LS > 0 && (64 % LS) == 0, "scan epilogue needs one slice per lane");
+    fifth_scan_apply<LS>(acc[0], s0, a.es);
+  }
+  if constexpr (EPI == 1) {
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
     if (active) {
 #pragma unroll
@@ -207,12 +212,12 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
   }
 }
 
-template <typename P, int LS, int NS, bool DAG, bool PRO, bool EPI>
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI>
 static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
   const int tps = a.Ls / NS;
   const int threads = cfg.spb * tps;
   const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
-  const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, EPI);
+  const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, EPI == 1);
   if (cfg.ll)
     hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
                        cfg.spb, cfg.xcd);
@@ -222,19 +227,20 @@ static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t s
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+template <typename P, int LS, int NS, bool DAG, bool PRO>
+static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
+  if (!a.E) return launch_hop_t<P, LS, NS, DAG, PRO, 0>(a, cfg, st);
+  if constexpr (NS == 1 && (LS == 8 || LS == 16 || LS == 32)) {
+    if (a.epi_scan) return launch_hop_t<P, LS, NS, DAG, PRO, 2>(a, cfg, st);
+  }
+  return launch_hop_t<P, LS, NS, DAG, PRO, 1>(a, cfg, st);
+}
+
 template <typename P, int LS, int NS>
 static int launch_hop_ns(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
-  const bool epi = a.E != nullptr;
-  if (dag) {
-    return epi ? launch_hop_t<P, LS, NS, true, false, true>(a, cfg, st)
-               : launch_hop_t<P, LS, NS, true, false, false>(a, cfg, st);
-  }
-  if (pro) {
-    return epi ? launch_hop_t<P, LS, NS, false, true, true>(a, cfg, st)
-               : launch_hop_t<P, LS, NS, false, true, false>(a, cfg, st);
-  }
-  return epi ? launch_hop_t<P, LS, NS, false, false, true>(a, cfg, st)
-             : launch_hop_t<P, LS, NS, false, false, false>(a, cfg, st);
+  if (dag) return launch_hop_epi<P, LS, NS, true, false>(a, cfg, st);
+  if (pro) return launch_hop_epi<P, LS, NS, false, true>(a, cfg, st);
+  return launch_hop_epi<P, LS, NS, false, false>(a, cfg, st);
 }
 
 // One compile-time fifth-dimension extent (0: runtime extent).  Each (precision, LS)
@@ -271,18 +277,47 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
 }
 
 // ------------------------------------------------------------------ site-local fifth-dimension matrices
-template <typename P>
-__global__ void __launch_bounds__(256) fifth_kernel(CHalf<P> in, Half<P> out, const typename P::R* E, CHalf<P> xin,
-                                                     typename P::R ax, long nsites, int Ls, int spb,
-                                                     double* norm_partials) {
+template <typename P, int LSEG>
+__global__ void __launch_bounds__(256) fifth_kernel(CHalf<P> in, Half<P> out, const typename P::R* E,
+                                                     FifthScan<typename P::R> es, CHalf<P> xin, typename P::R ax,
+                                                     long nsites, int Ls_rt, int spb, double* norm_partials) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
+  const int Ls = LSEG > 0 ? LSEG : Ls_rt;
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
   const int lsite = threadIdx.x / Ls;
   const int s = threadIdx.x - lsite * Ls;
   const long x = (long)blockIdx.x * spb + lsite;
   const bool active = (lsite < spb) && (x < nsites);
+  if constexpr (LSEG > 0) {
+    // recurrence form: the site's Ls lanes are one segment of the wave
+    cx<R> o[12];
+    if (active) load_spinor<P>(in, x, s, Ls, o);
+    else
+#pragma unroll
+      for (int k = 0; k < 12; ++k) o[k] = {R(0), R(0)};
+    fifth_scan_apply<LSEG>(o, s, es);
+    double nrm = 0.0;
+    if (active) {
+      if (xin.data) {
+        cx<R> xv[12];
+        load_spinor<P>(xin, x, s, Ls, xv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) o[k] = o[k] + ax * xv[k];
+      }
+      if (norm_partials) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nrm += double(o[k].re) * double(o[k].re) + double(o[k].im) * double(o[k].im);
+      }
+      store_spinor<P>(out, x, s, Ls, o);
+    }
+    if (norm_partials) {
+      const double t = block_sum(nrm, red);
+      if (threadIdx.x == 0) norm_partials[blockIdx.x] = t;
+    }
+    return;
+  }
   if (active) {
     cx<R> v[12];
     load_spinor<P>(in, x, s, Ls, v);
@@ -330,18 +365,35 @@ __global__ void __launch_bounds__(256) fifth_kernel(CHalf<P> in, Half<P> out, co
 }
 
 template <typename P>
-int launch_fifth(CHalf<P> in, Half<P> out, const typename P::R* E, CHalf<P> x, typename P::R ax, long nsites, int Ls,
-                 double* norm_partials, hipStream_t st) {
+int launch_fifth(CHalf<P> in, Half<P> out, const typename P::R* E, const FifthScan<typename P::R>* es, CHalf<P> x,
+                 typename P::R ax, long nsites, int Ls, double* norm_partials, hipStream_t st) {
   using R = typename P::R;
   if (Ls < 1 || Ls > 256) return -1;
+  if (nsites <= 0) return 0;
+  if (es && (Ls == 8 || Ls == 16 || Ls == 32)) {
+    // one slice per lane, sites aligned to wave segments (256 / Ls sites per workgroup)
+    const int spb = 256 / Ls;
+    const long blocks = (nsites + spb - 1) / spb;
+    FifthScan<R> e = *es;
+    if (Ls == 8)
+      hipLaunchKernelGGL((fifth_kernel<P, 8>), dim3((unsigned)blocks), dim3(256), 0, st, in, out, E, e, x, ax, nsites, Ls,
+                         spb, norm_partials);
+    else if (Ls == 16)
+      hipLaunchKernelGGL((fifth_kernel<P, 16>), dim3((unsigned)blocks), dim3(256), 0, st, in, out, E, e, x, ax, nsites,
+                         Ls, spb, norm_partials);
+    else
+      hipLaunchKernelGGL((fifth_kernel<P, 32>), dim3((unsigned)blocks), dim3(256), 0, st, in, out, E, e, x, ax, nsites,
+                         Ls, spb, norm_partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+  }
   int spb = 256 / Ls;
   if (spb < 1) spb = 1;
   while (spb > 1 && size_t(spb) * 12 * Ls * sizeof(cx<R>) > 65536) --spb;
-  if (nsites <= 0) return 0;
   const long blocks = (nsites + spb - 1) / spb;
   const size_t lds = size_t(spb) * 12 * Ls * sizeof(cx<R>);
-  hipLaunchKernelGGL((fifth_kernel<P>), dim3((unsigned)blocks), dim3(spb * Ls), lds, st, in, out, E, x, ax, nsites, Ls,
-                     spb, norm_partials);
+  FifthScan<R> e{};
+  hipLaunchKernelGGL((fifth_kernel<P, 0>), dim3((unsigned)blocks), dim3(spb * Ls), lds, st, in, out, E, e, x, ax, nsites,
+                     Ls, spb, norm_partials);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -363,5 +415,5 @@ inline long fifth_blocks(long nsites, int Ls, size_t elem) {
   DWF_HOP_LS_EXTERN(P, 0) DWF_HOP_LS_EXTERN(P, 8) DWF_HOP_LS_EXTERN(P, 12) DWF_HOP_LS_EXTERN(P, 16)               \
   DWF_HOP_LS_EXTERN(P, 32)                                                                                      \
   template int dwf::launch_hop<P>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);                \
-  template int dwf::launch_fifth<P>(CHalf<P>, Half<P>, const P::R*, CHalf<P>, P::R, long, int, double*,         \
-                                    hipStream_t);
+  template int dwf::launch_fifth<P>(CHalf<P>, Half<P>, const P::R*, const FifthScan<P::R>*, CHalf<P>, P::R,   \
+                                    long, int, double*, hipStream_t);

@@ -24,6 +24,8 @@ struct HopArgs {
   typename P::R scale;
   typename P::R pb, pc, pm;    // prologue F = pb + pc S~, boundary factor -pm
   const typename P::R* E;      // epilogue [2][Ls][Ls] or nullptr
+  FifthScan<typename P::R> es; // the same epilogue in recurrence form
+  int epi_scan;                // es is valid (used when the site's lanes form a wave segment)
   CHalf<P> x;                  // axpy operand (data == nullptr: none)
   typename P::R ax;
   double* norm_partials;       // per-block sum |out|^2 or nullptr
@@ -41,8 +43,8 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
 
 // out = ax * x + E . in  (site-local fifth-dimension matrices), optional |out|^2 partials
 template <typename P>
-int launch_fifth(CHalf<P> in, Half<P> out, const typename P::R* E, CHalf<P> x, typename P::R ax, long nsites,
-                 int Ls, double* norm_partials, hipStream_t st);
+int launch_fifth(CHalf<P> in, Half<P> out, const typename P::R* E, const FifthScan<typename P::R>* es, CHalf<P> x,
+                 typename P::R ax, long nsites, int Ls, double* norm_partials, hipStream_t st);
 
 // ---------------------------------------------------------------- BLAS-1 / reductions
 // Every reduction writes per-block FP64 partials; reduce_partials sums them in

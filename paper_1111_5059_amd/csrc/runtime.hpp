@@ -88,6 +88,7 @@ double read_scalar(dwf_ctx* ctx, const double* dscalars, int slot);
 
 // slots of the per-parameter fifth-dimension matrix table ([slot][2][Ls][Ls])
 enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_COUNT };
+bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, FifthScan<double>* out);
 
 template <typename P>
 size_t half_size(const Geometry* g, int Ls) { return half_bytes<P>(g->nsites, Ls); }
@@ -115,6 +116,8 @@ struct Op {
   bool moebius;  // F != 1
   const S* U[2];
   const R* E;
+  FifthScan<R> es[E_COUNT];  // the slots in recurrence form
+  bool scan_ok;
   LaunchCfg cfg;
 
   Op(dwf_ctx* ctx_, const Geometry* g_, const dwf_params& p, const void* packed_links)
@@ -125,6 +128,16 @@ struct Op {
     U[1] = base + size_t(g->nsites) * 72;
     E = reinterpret_cast<const R*>(fifth_matrices(ctx, Ls, M5, m, b, c, P::ID));
     cfg = hop_config(ctx, P::ID, Ls);
+    scan_ok = true;
+    for (int slot = 0; slot < E_COUNT; ++slot) {
+      FifthScan<double> e;
+      if (!fifth_scan(Ls, M5, m, b, c, slot, &e)) { scan_ok = false; break; }
+      es[slot].m = R(e.m);
+      for (int ch = 0; ch < 2; ++ch) {
+        const FifthChir<double>& q = e.ch[ch];
+        es[slot].ch[ch] = FifthChir<R>{R(q.a1), R(q.b1), R(q.inv_alpha), R(q.a), R(q.corr), q.d1, q.d2, q.has_inv};
+      }
+    }
   }
   const R* em(int slot) const { return E + size_t(slot) * 2 * Ls * Ls; }
   size_t hb() const { return half_size<P>(g, Ls); }
@@ -146,6 +159,11 @@ struct Op {
     a.pc = R(c);
     a.pm = R(m);
     a.E = epi;
+    a.epi_scan = 0;
+    if (epi && scan_ok) {
+      a.es = es[(epi - E) / (2 * Ls * Ls)];
+      a.epi_scan = 1;
+    }
     a.x = x;
     a.ax = R(ax);
     a.norm_partials = partials;
@@ -153,7 +171,8 @@ struct Op {
   }
   void fifth(CHalf<P> in, Half<P> out, int slot, CHalf<P> x = {nullptr, nullptr}, double ax = 0.0,
              double* partials = nullptr) const {
-    DWF_CHECK_LAUNCH(launch_fifth<P>(in, out, em(slot), x, R(ax), g->nsites, Ls, partials, ctx->stream));
+    DWF_CHECK_LAUNCH(launch_fifth<P>(in, out, em(slot), scan_ok ? &es[slot] : nullptr, x, R(ax), g->nsites, Ls,
+                                     partials, ctx->stream));
   }
   // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd)
   void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {

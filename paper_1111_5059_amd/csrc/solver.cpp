@@ -434,7 +434,7 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
       // A^-dag q into Ap (consumed by the next stage before Ap is overwritten)
       DWF_CHECK_LAUNCH(launch_fifth<Pi>(chview<Pi>(b.q, b.g, b.p.Ls), hview<Pi>(b.Ap, b.g, b.p.Ls),
                                         reinterpret_cast<const R*>(b.E) + size_t(E_AINVDAG) * 2 * b.p.Ls * b.p.Ls,
-                                        CHalf<Pi>{nullptr, nullptr}, R(0), b.g->nsites, b.p.Ls, nullptr, s));
+                                        nullptr, CHalf<Pi>{nullptr, nullptr}, R(0), b.g->nsites, b.p.Ls, nullptr, s));
     }
     DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[2], hg[2], dr[2], true, false, true, s));
     DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[3], hg[3], dr[3], true, false, moebius, s));
