@@ -64,6 +64,78 @@ __device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, c
   }
 }
 
+// FP16 storage without the prologue: the half spinor is formed in packed FP16 on the
+// norm-scaled values (one v_pk_add_f16 per colour and row, the factor i folded into the
+// operand selectors), the SU(3) product uses v_dot2_f32_f16 (two FP16 products accumulated
+// in FP32 per instruction), and the neighbour's norm is applied once in FP32.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f16x2 as_f16x2(const __half2& v) {
+  f16x2 r;
+  __builtin_memcpy(&r, &v, 4);
+  return r;
+}
+__device__ __forceinline__ f16x2 i_f16x2(f16x2 x) { return f16x2{-x.y, x.x}; }
+
+template <int MU, int SG>
+__device__ __forceinline__ void project_f16(const f16x2 p[12], f16x2 h[6]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const f16x2 p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    if constexpr (MU == 0) {
+      h[c] = SG > 0 ? p0 - i_f16x2(p3) : p0 + i_f16x2(p3);
+      h[3 + c] = SG > 0 ? p1 - i_f16x2(p2) : p1 + i_f16x2(p2);
+    } else if constexpr (MU == 1) {
+      h[c] = SG > 0 ? p0 - p3 : p0 + p3;
+      h[3 + c] = SG > 0 ? p1 + p2 : p1 - p2;
+    } else if constexpr (MU == 2) {
+      h[c] = SG > 0 ? p0 - i_f16x2(p2) : p0 + i_f16x2(p2);
+      h[3 + c] = SG > 0 ? p1 + i_f16x2(p3) : p1 - i_f16x2(p3);
+    } else {
+      h[c] = SG > 0 ? p0 + p2 : p0 - p2;
+      h[3 + c] = SG > 0 ? p1 + p3 : p1 - p3;
+    }
+  }
+}
+
+template <int MU, int SG, int NS, typename LPtr>
+__device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, LPtr L, int D, int s0, int tps,
+                                            cx<float> (&acc)[NS][12]) {
+  f16x2 U[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) U[e] = as_f16x2(L[D * 9 + e]);
+  const int Ls = a.Ls;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const int s = s0 + j * tps;
+    const __half2* p = a.in.data + size_t(y) * 12 * Ls + s;
+    f16x2 psi[12], h[6], hc[6], hs[6];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = as_f16x2(p[k * Ls]);
+    const float n = a.in.norm[size_t(y) * Ls + s];
+    project_f16<MU, SG>(psi, h);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      hc[k] = h[k] * f16x2{(_Float16)1, (_Float16)-1};  // (re, -im): real part of U h
+      hs[k] = h[k].yx;                                  // (im, re): imaginary part of U h
+    }
+    cx<float> u[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int row = 0; row < 3; ++row) {
+        float re = __builtin_amdgcn_fdot2(U[row * 3 + 0], hc[r * 3 + 0], 0.0f, false);
+        float im = __builtin_amdgcn_fdot2(U[row * 3 + 0], hs[r * 3 + 0], 0.0f, false);
+        re = __builtin_amdgcn_fdot2(U[row * 3 + 1], hc[r * 3 + 1], re, false);
+        im = __builtin_amdgcn_fdot2(U[row * 3 + 1], hs[r * 3 + 1], im, false);
+        re = __builtin_amdgcn_fdot2(U[row * 3 + 2], hc[r * 3 + 2], re, false);
+        im = __builtin_amdgcn_fdot2(U[row * 3 + 2], hs[r * 3 + 2], im, false);
+        u[r * 3 + row] = {n * re, n * im};
+      }
+    reconstruct_acc<MU, SG>(u, acc[j]);
+  }
+}
+
 // One of the 8 hop directions: D = 0..3 forward (x+mu), 4..7 backward (x-mu).
 // H uses (1 - g_mu) forward and (1 + g_mu) backward; H^dag the opposite.
 template <int D, bool DAG, bool PRO, int NS, typename P, typename LPtr>
@@ -74,6 +146,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, LPtr
   constexpr bool FWD = D < 4;
   constexpr int SG = (FWD != DAG) ? -1 : +1;
   const long y = nb[D];
+  if constexpr (std::is_same<P, P16>::value && !PRO) {
+    hop_dir_f16<MU, SG, NS>(a, y, L, D, s0, tps, acc);
+    return;
+  }
   cx<R> U[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) U[e] = P::ld(L[D * 9 + e]);
