@@ -49,7 +49,6 @@ def hop_bytes_per_site(prec, Ls):
     return b
 
 
-ROOFLINE_KERNEL = "hop_kernel<P32, 32, 1, false, false, false, true>"
 KERNEL_SOURCES = ("paper_1111_5059_amd/csrc/hop_impl.hpp", "paper_1111_5059_amd/csrc/device.hpp",
                   "paper_1111_5059_amd/csrc/kernels.hpp")
 
@@ -63,19 +62,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the roofline kernel from the committed hardware-counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or None when
-    the summary is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "hop_fp32_ls32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic_cfg3.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or None when the
+    summary is missing, lacks that kernel, or was taken on a different kernel source."""
     try:
-        with open(path) as fh:
+        with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def log(msg):
@@ -114,6 +116,29 @@ def time_hop(dwf, ctx, lat, U64, prec, reps=20):
     algo = hop_bytes_per_site(prec, lat.Ls) * nsites
     return {"ms": ms, "GBps": algo / (ms * 1e-3) / 1e9, "bytes_per_launch": algo, "sites": nsites,
             "GFLOPs": 1320.0 * nsites / (ms * 1e-3) / 1e9}
+
+
+def apply_operators(dwf, ctx, lat, inner, U64, prec, reps=5):
+    """M_prec and M_prec^dag of the target (DWF) and inner (Moebius) operators in storage
+    precision prec: launches every hop / fifth-dimension kernel variant of the solves."""
+    import torch
+    P = dwf.PREC_NAMES[prec]
+    Ug = lat.empty(dwf.KIND_GAUGE, P)
+    dwf.dwf_convert(ctx, lat.params(P), dwf.KIND_GAUGE, dwf.FP64, U64, P, Ug)
+    for lt, fn in ((lat, dwf.dwf_dslash), (inner, dwf.mobius_dslash)):
+        tmp = lt.zeros(dwf.KIND_ODD, dwf.FP64)
+        rng = torch.Generator(device="cuda")
+        rng.manual_seed(11)
+        tmp.view(torch.float64).normal_(generator=rng)
+        a = lt.empty(dwf.KIND_ODD, P)
+        dwf.dwf_convert(ctx, lt.params(P), dwf.KIND_ODD, dwf.FP64, tmp, P, a)
+        bb = lt.empty(dwf.KIND_ODD, P)
+        p = lt.params(P)
+        for _ in range(reps):
+            fn(ctx, p, Ug, a, bb, dwf.OP_MPREC, 0, False)
+            fn(ctx, p, Ug, bb, a, dwf.OP_MPREC, 0, True)
+        torch.cuda.synchronize()
+        del tmp, a, bb
 
 
 def cpu_baseline(workload, U, b_nat, fp64_iters, seconds_budget=25.0):
@@ -198,13 +223,18 @@ def main():
     torch.cuda.synchronize()
 
     if args.only_hop:
-        # a plain device copy of known size: calibrates FETCH_SIZE / WRITE_SIZE per byte
+        # the operator kernels of the solves, then a plain device copy of known size
+        # (calibrates FETCH_SIZE / WRITE_SIZE per byte)
+        apply_operators(dwf, ctx, lat, inner, U64, args.inner)
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         a.fill_(1)
         c = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         c.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"hop": hop, "copy_bytes": 1 << 30}))
+        print(json.dumps({"hop": hop, "copy_bytes": 1 << 30, "copy_GBps": 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e6)}))
         return
 
     # ---- plain FP64 CG (the comparison)
@@ -233,6 +263,9 @@ def main():
         info = step()
         log(f"warmup MADWF: {info['seconds']:.2f} s")
     torch.cuda.synchronize()
+    # per-launch HIP events around the hop / fifth-dimension kernels, on the library's stream
+    dwf.dwf_timing_report(ctx)
+    dwf.dwf_timing_enable(ctx, True)
     t = time.perf_counter()
     infos = []
     for k in range(args.steps):
@@ -240,6 +273,9 @@ def main():
         log(f"step {k}: {infos[-1]['seconds']:.2f} s, resid {infos[-1]['true_rel_resid']:.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
+    kt = dwf.dwf_timing_report(ctx)
+    dwf.dwf_timing_enable(ctx, False)
+    dom = max(kt, key=lambda k: kt[k]["ms"]) if kt else None
     sec = elapsed / max(1, args.steps)
     last = infos[-1] if infos else {}
     converged = all(i["converged"] and i["true_rel_resid"] <= 1e-10 for i in infos)
@@ -250,8 +286,17 @@ def main():
         cpu = cpu_baseline(WORKLOADS[args.workload], U, b_nat, fp64["iters"])
         log(f"oracle: {cpu['seconds_per_iteration']:.2f} s per CG iteration on {cpu['cores']} threads")
 
-    rf = hop.get("fp32", {"GBps": 0.0, "bytes_per_launch": 0.0, "ms": 0.0})
-    traffic = measured_traffic()
+    roof = None
+    if dom is not None:
+        d = kt[dom]
+        bpl, avg_ms = d["bytes"] / d["launches"], d["ms"] / d["launches"]
+        achieved = bpl / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(dom)
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                "launches_per_step": d["launches"] / max(1, args.steps), "bytes_per_launch": bpl,
+                "avg_launch_ms": avg_ms, "share_of_step": d["ms"] * 1e-3 / elapsed}
+        log(f"dominant kernel {dom}: {d['launches']} launches, {avg_ms:.3f} ms avg, {achieved:.0f} GB/s")
     out = {
         "metric": METRIC,
         "value": sec,
@@ -275,10 +320,10 @@ def main():
         "wilson_apps_ratio_fp64_over_madwf": (fp64["wilson_apps"] / last["wilson_apps"]) if fp64 and last else None,
         "dslash": {k: {"GBps": v["GBps"], "pct_hbm_peak": 100 * v["GBps"] / HBM_PEAK_GBS, "GFLOPs": v["GFLOPs"],
                        "ms": v["ms"]} for k, v in hop.items()},
-        "roofline": {"bound": "hbm", "achieved": rf["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rf["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "hop_kernel<P32,1,false,false,false> (Wilson hop, FP32, half lattice)",
-                     "bytes_per_launch": rf["bytes_per_launch"], "avg_launch_ms": rf["ms"]},
+        "roofline": roof,
+        "kernels_in_step": {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
+                                "GBps": v["bytes"] / (v["ms"] * 1e6), "share_of_step": v["ms"] * 1e-3 / elapsed}
+                            for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["ms"])},
         "cpu_baseline": cpu,
         "paper_context": "Table 1 (BG/P, 512 nodes, 32^3x64, L=32 -> L'=12): 1.8x fewer 4D Wilson "
                          "applications, 42% of the direct-CG wall time",

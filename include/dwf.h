@@ -202,6 +202,20 @@ int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_bl
 int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* sites_per_block, int* s_per_thread,
                  int* xcd_remap, int* link_lds);
 
+/* Measurement.  dwf_timing_enable(ctx, 1) starts recording a HIP event pair on the
+ * context stream around every Wilson-hop and fifth-dimension kernel launch the
+ * context makes (the events add a few microseconds between launches);
+ * dwf_timing_enable(ctx, 0) stops recording and discards the records.
+ * dwf_timing_report synchronizes the context stream and writes one line per
+ * kernel variant launched since the last report,
+ *   "<kernel name>\t<launches>\t<total ms>\t<total algorithmic bytes>\n",
+ * into buf (NUL-terminated; the kernel name is the template instance as
+ * profilers print it; algorithmic bytes count each input and output field and
+ * the links once per launch), then clears the records.  Returns DWF_ERR_ARG if
+ * buf is NULL or len is too small (the records are then lost). */
+int dwf_timing_enable(dwf_ctx* ctx, int enable);
+int dwf_timing_report(dwf_ctx* ctx, char* buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

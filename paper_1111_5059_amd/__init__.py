@@ -84,6 +84,8 @@ SIGNATURES = {
     "fermion_force": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(_cd), _cd, _ci, _vp, ctypes.POINTER(SolveInfo)], _ci),
     "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci, _ci, _ci], _ci),
     "dwf_tune_get": ([_vp, _ci, _ci, _ci] + [ctypes.POINTER(_ci)] * 4, _ci),
+    "dwf_timing_enable": ([_vp, _ci], _ci),
+    "dwf_timing_report": ([_vp, ctypes.c_char_p, ctypes.c_size_t], _ci),
 }
 
 
@@ -243,6 +245,22 @@ def dwf_tune_get(ctx, prec, Ls, kernel_id=0):
     v = [_ci(0) for _ in range(4)]
     _check(lib().dwf_tune_get(ctx.handle, int(kernel_id), int(prec), int(Ls), *[ctypes.byref(t) for t in v]))
     return tuple(t.value for t in v)
+
+
+def dwf_timing_enable(ctx, enable=True):
+    _check(lib().dwf_timing_enable(ctx.handle, int(bool(enable))))
+
+
+def dwf_timing_report(ctx):
+    """{kernel name: {"launches", "ms", "bytes"}} for the hop / fifth-dimension launches
+    since the last report (HIP events on the context stream)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().dwf_timing_report(ctx.handle, buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms, nbytes = line.split("\t")
+        out[name] = {"launches": int(n), "ms": float(ms), "bytes": float(nbytes)}
+    return out
 
 
 from .fields import Lattice  # noqa: E402,F401

@@ -455,6 +455,7 @@ template int launch_cg_update<P16, P32>(Half<P32>, CHalf<P16>, Half<P16>, CHalf<
 template int launch_cg_update<PB16, P32>(Half<P32>, CHalf<PB16>, Half<PB16>, CHalf<PB16>, const double*, long, int,
                                          double*, hipStream_t);
 template int launch_accumulate<P32>(Half<P64>, Half<P32>, long, int, hipStream_t);
+template int launch_accumulate<P16>(Half<P64>, Half<P16>, long, int, hipStream_t);
 template int launch_accumulate<P64>(Half<P64>, Half<P64>, long, int, hipStream_t);
 
 }  // namespace dwf

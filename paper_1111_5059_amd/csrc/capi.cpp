@@ -192,6 +192,7 @@ int dwf_ctx_destroy(dwf_ctx* ctx) {
     for (auto& kv : ctx->ws) (void)hipFree(kv.second.first);
     for (auto& kv : ctx->emats) (void)hipFree(kv.second.first);
     ctx->geoms.clear();
+    timer_release(ctx);
     if (ctx->h_scalars) (void)hipHostFree(ctx->h_scalars);
     delete ctx;
     return DWF_OK;
@@ -396,7 +397,8 @@ int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns,
   if (spb < 1 || spb * (Ls / ns) > 256) return fail(DWF_ERR_ARG, "sites_per_block * Ls / s_per_thread must be <= 256");
   const size_t elem = prec == DWF_FP64 ? 16 : 8;
   const size_t lelem = prec == DWF_FP64 ? 16 : prec == DWF_FP32 ? 8 : 4;
-  if (size_t(spb) * 12 * Ls * elem + (ll ? size_t(spb) * 72 * lelem : 0) > 65536)
+  const size_t lsite = prec == DWF_FP16 ? 160 : 72;  // FP16 links are staged in two forms
+  if (size_t(spb) * 12 * Ls * elem + (ll ? size_t(spb) * lsite * lelem : 0) > 65536)
     return fail(DWF_ERR_ARG, "workgroup LDS (epilogue + staged links) exceeds 64 KiB");
   LaunchCfg c;
   c.spb = spb;
@@ -416,6 +418,33 @@ int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* spb, int* n
   *xcd = c.xcd;
   *ll = c.ll;
   return DWF_OK;
+}
+
+int dwf_timing_enable(dwf_ctx* ctx, int enable) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  return guarded([&]() {
+    if (!enable) {
+      DWF_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+      ctx->timer.marks.clear();
+      ctx->timer.used = 0;
+    }
+    ctx->timer.on = enable != 0;
+    return DWF_OK;
+  });
+}
+
+int dwf_timing_report(dwf_ctx* ctx, char* buf, size_t len) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  if (!buf || len == 0) return fail(DWF_ERR_ARG, "NULL report buffer");
+  return guarded([&]() {
+    const std::string r = timer_report(ctx);
+    if (r.size() + 1 > len) {
+      buf[0] = 0;
+      return fail(DWF_ERR_ARG, "report buffer too small: need " + std::to_string(r.size() + 1) + " bytes");
+    }
+    std::memcpy(buf, r.c_str(), r.size() + 1);
+    return DWF_OK;
+  });
 }
 
 }  // extern "C"

@@ -33,6 +33,70 @@ double read_scalar(dwf_ctx* ctx, const double* dscalars, int slot) {
   return ctx->h_scalars[slot];
 }
 
+long timer_begin(dwf_ctx* ctx, const std::string& kernel) {
+  KernelTimer& t = ctx->timer;
+  if (!t.on) return -1;
+  auto it = t.ids.find(kernel);
+  int cls;
+  if (it == t.ids.end()) {
+    cls = int(t.names.size());
+    t.names.push_back(kernel);
+    t.ids[kernel] = cls;
+  } else {
+    cls = it->second;
+  }
+  while (t.pool.size() < t.used + 2) {
+    hipEvent_t e;
+    DWF_CHECK_HIP(hipEventCreate(&e));
+    t.pool.push_back(e);
+  }
+  const size_t e0 = t.used++;
+  DWF_CHECK_HIP(hipEventRecord(t.pool[e0], ctx->stream));
+  t.marks.push_back({cls, e0, 0, 0.0});
+  return long(t.marks.size()) - 1;
+}
+
+void timer_end(dwf_ctx* ctx, long mark, double bytes) {
+  KernelTimer& t = ctx->timer;
+  if (mark < 0 || size_t(mark) >= t.marks.size()) return;
+  const size_t e1 = t.used++;
+  DWF_CHECK_HIP(hipEventRecord(t.pool[e1], ctx->stream));
+  t.marks[mark].e1 = e1;
+  t.marks[mark].bytes = bytes;
+}
+
+std::string timer_report(dwf_ctx* ctx) {
+  KernelTimer& t = ctx->timer;
+  DWF_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<long long> n(t.names.size(), 0);
+  std::vector<double> ms(t.names.size(), 0.0), bytes(t.names.size(), 0.0);
+  for (const auto& m : t.marks) {
+    float e = 0.f;
+    DWF_CHECK_HIP(hipEventElapsedTime(&e, t.pool[m.e0], t.pool[m.e1]));
+    n[m.cls] += 1;
+    ms[m.cls] += e;
+    bytes[m.cls] += m.bytes;
+  }
+  std::string out;
+  char line[64];
+  for (size_t c = 0; c < t.names.size(); ++c) {
+    if (!n[c]) continue;
+    snprintf(line, sizeof(line), "\t%lld\t%.6f\t%.6e\n", n[c], ms[c], bytes[c]);
+    out += t.names[c] + line;
+  }
+  t.marks.clear();
+  t.used = 0;
+  return out;
+}
+
+void timer_release(dwf_ctx* ctx) {
+  KernelTimer& t = ctx->timer;
+  for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
+  t.pool.clear();
+  t.marks.clear();
+  t.used = 0;
+}
+
 // 4D checkerboard tables.  Lexicographic index i = x + X(y + Y(z + Z t)), parity
 // (x+y+z+t) mod 2, x_cb = i / 2 (X even).  For output parity p and site x_cb:
 // nbr = x_cb of x +- mu (in the other parity), linksrc = code of the link the hop
@@ -127,7 +191,8 @@ LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls) {
   while (spb > 1 && (spb * Ls) % 64 != 0) --spb;
   if ((spb * Ls) % 64 != 0) spb = 256 / Ls > 0 ? 256 / Ls : 1;
   // the workgroup's LDS (epilogue staging + staged links) must fit in 64 KiB
-  const size_t per_site = size_t(12) * Ls * (prec == 0 ? 16 : 8) + 72 * (prec == 0 ? 16 : prec == 1 ? 8 : 4);
+  // (FP16 links are staged in two forms: 160 elements per site)
+  const size_t per_site = size_t(12) * Ls * (prec == 0 ? 16 : 8) + (prec == 2 ? 160 : 72) * (prec == 0 ? 16 : prec == 1 ? 8 : 4);
   while (spb > 1 && spb * per_site > 65536) spb /= 2;
   c.spb = spb;
   return c;

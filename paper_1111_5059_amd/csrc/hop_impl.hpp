@@ -35,11 +35,15 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// dynamic LDS of one hop workgroup: epilogue staging + staged links
+// LDS elements per site of the staged links: FP16 links are staged as (Uc, Us) pairs
+template <typename P>
+constexpr int staged_link_elems() { return std::is_same<P, P16>::value ? 160 : 72; }
+
+// dynamic LDS of one hop workgroup: dense-epilogue staging + staged links
 template <typename P>
 inline size_t hop_lds_bytes(const LaunchCfg& cfg, int Ls, bool epi) {
   size_t b = epi ? size_t(cfg.spb) * 12 * Ls * sizeof(cx<typename P::R>) : 0;
-  if (cfg.ll) b += size_t(cfg.spb) * 72 * sizeof(typename P::S);
+  if (cfg.ll) b += size_t(cfg.spb) * staged_link_elems<P>() * sizeof(typename P::S);
   return b;
 }
 
@@ -64,10 +68,11 @@ __device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, c
   }
 }
 
-// FP16 storage without the prologue: the half spinor is formed in packed FP16 on the
-// norm-scaled values (one v_pk_add_f16 per colour and row, the factor i folded into the
-// operand selectors), the SU(3) product uses v_dot2_f32_f16 (two FP16 products accumulated
-// in FP32 per instruction), and the neighbour's norm is applied once in FP32.
+// FP16 storage: the half spinor is formed in packed FP16 on the norm-scaled values (one
+// v_pk_add_f16 per colour and row, the factor i folded into the operand selectors), the
+// SU(3) product uses v_dot2_f32_f16 (two FP16 products accumulated in FP32 per
+// instruction) on link elements the workgroup stages in the two forms the real and the
+// imaginary part need, and the neighbour's norm is applied in the FP32 accumulation.
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ f16x2 as_f16x2(const __half2& v) {
@@ -75,7 +80,22 @@ __device__ __forceinline__ f16x2 as_f16x2(const __half2& v) {
   __builtin_memcpy(&r, &v, 4);
   return r;
 }
+__device__ __forceinline__ __half2 from_f16x2(f16x2 v) {
+  __half2 r;
+  __builtin_memcpy(&r, &v, 4);
+  return r;
+}
 __device__ __forceinline__ f16x2 i_f16x2(f16x2 x) { return f16x2{-x.y, x.x}; }
+
+// One row of the SU(3) product: three v_dot2_f32_f16 chained through the FP32 accumulator,
+// on link elements staged as uc = (Ur, -Ui) for the real part, Ur hr - Ui hi, and
+// us = (Ui, Ur) for the imaginary part, Ui hr + Ur hi (builtins, so that the compiler sees
+// the DOT instructions and inserts the wait states their results need).
+__device__ __forceinline__ float row_dot(f16x2 u0, f16x2 u1, f16x2 u2, f16x2 h0, f16x2 h1, f16x2 h2) {
+  float r = __builtin_amdgcn_fdot2(u0, h0, 0.0f, false);
+  r = __builtin_amdgcn_fdot2(u1, h1, r, false);
+  return __builtin_amdgcn_fdot2(u2, h2, r, false);
+}
 
 template <int MU, int SG>
 __device__ __forceinline__ void project_f16(const f16x2 p[12], f16x2 h[6]) {
@@ -98,61 +118,128 @@ __device__ __forceinline__ void project_f16(const f16x2 p[12], f16x2 h[6]) {
   }
 }
 
-template <int MU, int SG, int NS, typename LPtr>
-__device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, LPtr L, int D, int s0, int tps,
-                                            cx<float> (&acc)[NS][12]) {
-  f16x2 U[9];
+// acc += n * reconstruction of u = (re, im): reconstruct_acc with the neighbour norm folded
+// into fused multiply-adds
+template <int MU, int SG>
+__device__ __forceinline__ void reconstruct_fma(const float re[6], const float im[6], float n, cx<float> acc[12]) {
+  const float sn = SG * n;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) U[e] = as_f16x2(L[D * 9 + e]);
+  for (int c = 0; c < 3; ++c) {
+    const float r0 = re[c], i0 = im[c], r1 = re[3 + c], i1 = im[3 + c];
+    acc[c] = {fmaf(n, r0, acc[c].re), fmaf(n, i0, acc[c].im)};
+    acc[3 + c] = {fmaf(n, r1, acc[3 + c].re), fmaf(n, i1, acc[3 + c].im)};
+    if constexpr (MU == 0) {  // + sg i u1, + sg i u0
+      acc[6 + c] = {fmaf(-sn, i1, acc[6 + c].re), fmaf(sn, r1, acc[6 + c].im)};
+      acc[9 + c] = {fmaf(-sn, i0, acc[9 + c].re), fmaf(sn, r0, acc[9 + c].im)};
+    } else if constexpr (MU == 1) {  // + sg u1, - sg u0
+      acc[6 + c] = {fmaf(sn, r1, acc[6 + c].re), fmaf(sn, i1, acc[6 + c].im)};
+      acc[9 + c] = {fmaf(-sn, r0, acc[9 + c].re), fmaf(-sn, i0, acc[9 + c].im)};
+    } else if constexpr (MU == 2) {  // + sg i u0, - sg i u1
+      acc[6 + c] = {fmaf(-sn, i0, acc[6 + c].re), fmaf(sn, r0, acc[6 + c].im)};
+      acc[9 + c] = {fmaf(sn, i1, acc[9 + c].re), fmaf(-sn, r1, acc[9 + c].im)};
+    } else {  // + sg u0, + sg u1
+      acc[6 + c] = {fmaf(sn, r0, acc[6 + c].re), fmaf(sn, i0, acc[6 + c].im)};
+      acc[9 + c] = {fmaf(sn, r1, acc[9 + c].re), fmaf(sn, i1, acc[9 + c].im)};
+    }
+  }
+}
+
+// the link elements of one direction as (Uc, Us) = ((Ur, -Ui), (Ui, Ur)): staged in LDS in
+// pairs (stride 20 per direction) or formed from the packed field (stride 9)
+template <bool PAIRED>
+__device__ __forceinline__ void links_f16(const __half2* L, int D, f16x2 Uc[9], f16x2 Us[9]) {
+  if constexpr (PAIRED) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      Uc[e] = as_f16x2(L[D * 20 + 2 * e]);
+      Us[e] = as_f16x2(L[D * 20 + 2 * e + 1]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      const f16x2 u = as_f16x2(L[D * 9 + e]);
+      Uc[e] = u * f16x2{(_Float16)1, (_Float16)-1};
+      Us[e] = u.yx;
+    }
+  }
+}
+
+// Moebius input factor F = b + c S~ on one FP16 neighbour spinor, in packed FP16: the three
+// terms (psi_s, the upper spins of psi_{s-1}, the lower spins of psi_{s+1}, each with its own
+// norm) are weighted relative to the largest weight, so every packed value stays within the
+// FP16 range (|value| <= 2); the largest weight is returned as the norm of the result.
+__device__ __forceinline__ float load_input_f16_pro(const HopArgs<P16>& a, long y, int s, f16x2 psi[12]) {
+  const int Ls = a.Ls;
+  const __half2* p = a.in.data + size_t(y) * 12 * Ls;
+  const float* nb = a.in.norm + size_t(y) * Ls;
+  int su = s - 1, sl = s + 1;
+  float fu = a.pc, fl = a.pc;
+  if (su < 0) { su = Ls - 1; fu = -a.pc * a.pm; }
+  if (sl >= Ls) { sl = 0; fl = -a.pc * a.pm; }
+  const float ws = a.pb * nb[s], wu = fu * nb[su], wl = fl * nb[sl];
+  const float m = fmaxf(fabsf(ws), fmaxf(fabsf(wu), fabsf(wl)));
+  const float inv = m > 1e-37f ? __builtin_amdgcn_rcpf(m) : 0.0f;  // (ratios only need FP16 accuracy)
+  const _Float16 hs = (_Float16)(ws * inv), hu = (_Float16)(wu * inv), hl = (_Float16)(wl * inv);
+  const f16x2 cs = {hs, hs}, cu = {hu, hu}, cl = {hl, hl};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) psi[k] = cs * as_f16x2(p[k * Ls + s]) + cu * as_f16x2(p[k * Ls + su]);
+#pragma unroll
+  for (int k = 6; k < 12; ++k) psi[k] = cs * as_f16x2(p[k * Ls + s]) + cl * as_f16x2(p[k * Ls + sl]);
+  return m;
+}
+
+template <int MU, int SG, int NS, bool PRO, bool PAIRED>
+__device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const __half2* L, int D, int s0, int tps,
+                                            cx<float> (&acc)[NS][12]) {
+  f16x2 Uc[9], Us[9];
+  links_f16<PAIRED>(L, D, Uc, Us);
   const int Ls = a.Ls;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     const int s = s0 + j * tps;
-    const __half2* p = a.in.data + size_t(y) * 12 * Ls + s;
-    f16x2 psi[12], h[6], hc[6], hs[6];
+    f16x2 psi[12], h[6];
+    float n;
+    if constexpr (PRO) {
+      n = load_input_f16_pro(a, y, s, psi);
+    } else {
+      const __half2* p = a.in.data + size_t(y) * 12 * Ls + s;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) psi[k] = as_f16x2(p[k * Ls]);
-    const float n = a.in.norm[size_t(y) * Ls + s];
-    project_f16<MU, SG>(psi, h);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      hc[k] = h[k] * f16x2{(_Float16)1, (_Float16)-1};  // (re, -im): real part of U h
-      hs[k] = h[k].yx;                                  // (im, re): imaginary part of U h
+      for (int k = 0; k < 12; ++k) psi[k] = as_f16x2(p[k * Ls]);
+      n = a.in.norm[size_t(y) * Ls + s];
     }
-    cx<float> u[6];
+    n *= a.scale;  // the hop's overall scale folded in
+    project_f16<MU, SG>(psi, h);
+    float re[6], im[6];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int row = 0; row < 3; ++row) {
-        float re = __builtin_amdgcn_fdot2(U[row * 3 + 0], hc[r * 3 + 0], 0.0f, false);
-        float im = __builtin_amdgcn_fdot2(U[row * 3 + 0], hs[r * 3 + 0], 0.0f, false);
-        re = __builtin_amdgcn_fdot2(U[row * 3 + 1], hc[r * 3 + 1], re, false);
-        im = __builtin_amdgcn_fdot2(U[row * 3 + 1], hs[r * 3 + 1], im, false);
-        re = __builtin_amdgcn_fdot2(U[row * 3 + 2], hc[r * 3 + 2], re, false);
-        im = __builtin_amdgcn_fdot2(U[row * 3 + 2], hs[r * 3 + 2], im, false);
-        u[r * 3 + row] = {n * re, n * im};
+        re[r * 3 + row] = row_dot(Uc[row * 3], Uc[row * 3 + 1], Uc[row * 3 + 2], h[r * 3], h[r * 3 + 1], h[r * 3 + 2]);
+        im[r * 3 + row] = row_dot(Us[row * 3], Us[row * 3 + 1], Us[row * 3 + 2], h[r * 3], h[r * 3 + 1], h[r * 3 + 2]);
       }
-    reconstruct_acc<MU, SG>(u, acc[j]);
+    reconstruct_fma<MU, SG>(re, im, n, acc[j]);
   }
 }
 
 // One of the 8 hop directions: D = 0..3 forward (x+mu), 4..7 backward (x-mu).
 // H uses (1 - g_mu) forward and (1 + g_mu) backward; H^dag the opposite.
-template <int D, bool DAG, bool PRO, int NS, typename P, typename LPtr>
-__device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, LPtr L, int s0, int tps,
+// PAIRED: FP16 links staged as (U, Us) pairs, 20 elements per direction.
+template <int D, bool DAG, bool PRO, int NS, bool PAIRED, typename P>
+__device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, const typename P::S* L, int s0, int tps,
                                         cx<typename P::R> (&acc)[NS][12]) {
   using R = typename P::R;
   constexpr int MU = D & 3;
   constexpr bool FWD = D < 4;
   constexpr int SG = (FWD != DAG) ? -1 : +1;
   const long y = nb[D];
-  if constexpr (std::is_same<P, P16>::value && !PRO) {
-    hop_dir_f16<MU, SG, NS>(a, y, L, D, s0, tps, acc);
+  if constexpr (std::is_same<P, P16>::value) {
+    hop_dir_f16<MU, SG, NS, PRO, PAIRED>(a, y, L, D, s0, tps, acc);
     return;
   }
+  constexpr int LSTR = PAIRED ? 20 : 9, LEL = PAIRED ? 2 : 1;
   cx<R> U[9];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) U[e] = P::ld(L[D * 9 + e]);
+  for (int e = 0; e < 9; ++e) U[e] = P::ld(L[D * LSTR + e * LEL]);
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     cx<R> psi[12], h[6], u[6];
@@ -163,7 +250,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, LPtr
   }
 }
 
-template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL>
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG>
 __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -184,11 +271,13 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[j][k] = {R(0), R(0)};
   using S = typename P::S;
+  constexpr bool PAIRED = LL && std::is_same<P, P16>::value;
   const S* L;
   if constexpr (LL) {
     // Stage the 8 links of each of the workgroup's sites in LDS with coalesced loads
     // (one read per element instead of one per s-slice lane); lanes then read them
     // through the LDS pipe, which leaves the texture-data path to the spinors.
+    constexpr int NE = staged_link_elems<P>();
     S* llds = reinterpret_cast<S*>(smem_raw + (EPI == 1 ? size_t(spb) * 12 * Ls * sizeof(cx<R>) : 0));
     const long base = bid * spb;
     for (int i = threadIdx.x; i < spb * 72; i += blockDim.x) {
@@ -196,29 +285,40 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
       const long sl = base + ls;
       if (sl < a.nsites) {
         const long xs = a.order ? long(a.order[sl]) : sl;
-        llds[i] = a.links[xs * 72 + (i - ls * 72)];
+        const int j = i - ls * 72;
+        const S u = a.links[xs * 72 + j];
+        if constexpr (PAIRED) {
+          const int d = j / 9, e = j - d * 9;
+          const f16x2 v = as_f16x2(u);
+          llds[ls * NE + d * 20 + 2 * e] = from_f16x2(v * f16x2{(_Float16)1, (_Float16)-1});
+          llds[ls * NE + d * 20 + 2 * e + 1] = from_f16x2(v.yx);
+        } else {
+          llds[i] = u;
+        }
       }
     }
     __syncthreads();
-    L = llds + lsite * 72;
+    L = llds + lsite * NE;
   } else {
     L = a.links + x * 72;
   }
   if (active) {
     const int* nb = a.nbr + x * 8;
-    hop_dir<0, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<1, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<2, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<3, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<4, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<5, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<6, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
-    hop_dir<7, DAG, PRO, NS>(ak, nb, L, s0, tps, acc);
+    hop_dir<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<1, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<2, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<3, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<4, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<5, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<6, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    hop_dir<7, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
   }
+  if constexpr (!std::is_same<P, P16>::value) {  // (the FP16 path folds the scale into the norm)
 #pragma unroll
-  for (int j = 0; j < NS; ++j)
+    for (int j = 0; j < NS; ++j)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
+      for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
+  }
   if constexpr (EPI == 2) {
     // recurrence form along s: the site's Ls lanes are one segment of the wave
     static_assert(NS == 1 && LS > 0 && (64 % LS) == 0, "scan epilogue needs one slice per lane");
@@ -265,6 +365,7 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
   }
   double nrm = 0.0;
   if (active) {
+    const R alpha = CG ? R(a.cg_scalars[S_ALPHA]) : R(0);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const int s = s0 + j * tps;
@@ -274,12 +375,35 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[j][k] = acc[j][k] + a.ax * xv[k];
       }
-      if (a.norm_partials) {
+      if constexpr (CG) {
+        // r -= alpha v, xl += alpha p: the CG vector updates on the site this thread holds
+        using PX = typename IncrementPrec<P>::type;
+        using RX = typename PX::R;
+        cx<R> rv[12], pv[12];
+        cx<RX> xl[12];
+        load_spinor<P>(CHalf<P>{a.cg_r.data, a.cg_r.norm}, x, s, Ls, rv);
+        load_spinor<P>(a.cg_p, x, s, Ls, pv);
+        load_spinor<PX>(CHalf<PX>{a.cg_x.data, a.cg_x.norm}, x, s, Ls, xl);
 #pragma unroll
-        for (int k = 0; k < 12; ++k)
-          nrm += double(acc[j][k].re) * double(acc[j][k].re) + double(acc[j][k].im) * double(acc[j][k].im);
+        for (int k = 0; k < 12; ++k) {
+          rv[k] = {rv[k].re - alpha * acc[j][k].re, rv[k].im - alpha * acc[j][k].im};
+          xl[k] = {xl[k].re + RX(alpha) * RX(pv[k].re), xl[k].im + RX(alpha) * RX(pv[k].im)};
+        }
+        store_spinor<PX>(a.cg_x, x, s, Ls, xl);
+        store_spinor<P>(a.cg_r, x, s, Ls, rv);
+        if (a.norm_partials) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k)
+            nrm += double(rv[k].re) * double(rv[k].re) + double(rv[k].im) * double(rv[k].im);
+        }
+      } else {
+        if (a.norm_partials) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k)
+            nrm += double(acc[j][k].re) * double(acc[j][k].re) + double(acc[j][k].im) * double(acc[j][k].im);
+        }
+        store_spinor<P>(a.out, x, s, Ls, acc[j]);
       }
-      store_spinor<P>(a.out, x, s, Ls, acc[j]);
     }
   }
   if (a.norm_partials) {
@@ -288,35 +412,39 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
   }
 }
 
-template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI>
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool CG>
 static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
   const int tps = a.Ls / NS;
   const int threads = cfg.spb * tps;
   const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
   const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, EPI == 1);
   if (cfg.ll)
-    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
-                       cfg.spb, cfg.xcd);
+    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true, CG>), dim3((unsigned)blocks), dim3(threads), lds, st,
+                       a, cfg.spb, cfg.xcd);
   else
-    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, false>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
-                       cfg.spb, cfg.xcd);
+    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, false, CG>), dim3((unsigned)blocks), dim3(threads), lds,
+                       st, a, cfg.spb, cfg.xcd);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template <typename P, int LS, int NS, bool DAG, bool PRO>
+template <typename P, int LS, int NS, bool DAG, bool PRO, bool CG>
 static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
-  if (!a.E) return launch_hop_t<P, LS, NS, DAG, PRO, 0>(a, cfg, st);
+  if (!a.E) return launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st);
   if constexpr (NS == 1 && (LS == 8 || LS == 16 || LS == 32)) {
-    if (a.epi_scan) return launch_hop_t<P, LS, NS, DAG, PRO, 2>(a, cfg, st);
+    if (a.epi_scan) return launch_hop_t<P, LS, NS, DAG, PRO, 2, CG>(a, cfg, st);
   }
-  return launch_hop_t<P, LS, NS, DAG, PRO, 1>(a, cfg, st);
+  return launch_hop_t<P, LS, NS, DAG, PRO, 1, CG>(a, cfg, st);
 }
 
+// the fused CG step exists for the dagger hop only (the last hop of M^dag M)
 template <typename P, int LS, int NS>
 static int launch_hop_ns(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
-  if (dag) return launch_hop_epi<P, LS, NS, true, false>(a, cfg, st);
-  if (pro) return launch_hop_epi<P, LS, NS, false, true>(a, cfg, st);
-  return launch_hop_epi<P, LS, NS, false, false>(a, cfg, st);
+  if (dag) {
+    if (a.cg_r.data) return launch_hop_epi<P, LS, NS, true, false, true>(a, cfg, st);
+    return launch_hop_epi<P, LS, NS, true, false, false>(a, cfg, st);
+  }
+  if (pro) return launch_hop_epi<P, LS, NS, false, true, false>(a, cfg, st);
+  return launch_hop_epi<P, LS, NS, false, false, false>(a, cfg, st);
 }
 
 // One compile-time fifth-dimension extent (0: runtime extent).  Each (precision, LS)
@@ -338,6 +466,7 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
   if (cfg.ns != 1 && cfg.ns != 2 && cfg.ns != 4) return -1;
   if (a.Ls % cfg.ns != 0 || cfg.spb < 1) return -1;
   if (dagger && prologue) return -1;
+  if (a.cg_r.data && (!dagger || !a.cg_p.data || !a.cg_x.data || !a.cg_scalars)) return -1;
   const int threads = cfg.spb * (a.Ls / cfg.ns);
   if (threads > 256) return -1;
   if (hop_lds_bytes<P>(cfg, a.Ls, a.E != nullptr) > 65536) return -1;

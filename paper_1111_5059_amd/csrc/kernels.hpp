@@ -6,6 +6,19 @@
 
 namespace dwf {
 
+// Storage precision of the CG solution increment accumulated between reliable updates for
+// iterations in storage precision P: FP32 (an FP16 increment would carry errors of relative
+// size 2^-11 in every eigen-direction of M^dag M, which the condition number amplifies in
+// the residual), FP64 for FP64 iterations.
+template <typename P>
+struct IncrementPrec {
+  using type = P32;
+};
+template <>
+struct IncrementPrec<P64> {
+  using type = P64;
+};
+
 // Arguments of one Wilson-hop launch over a half field (output parity fixed by
 // the link block and neighbour table handed in).
 //   out = ax * x + E . (scale * H F in)       (H^dag when dagger)
@@ -28,7 +41,13 @@ struct HopArgs {
   int epi_scan;                // es is valid (used when the site's lanes form a wave segment)
   CHalf<P> x;                  // axpy operand (data == nullptr: none)
   typename P::R ax;
-  double* norm_partials;       // per-block sum |out|^2 or nullptr
+  double* norm_partials;       // per-block sum |out|^2 (|cg_r|^2 with the fused CG step) or nullptr
+  // CG step fused into the last hop of M^dag M p (cg_r.data == nullptr: none).  With it the
+  // result v is not stored; instead r -= alpha v and xl += alpha p, alpha = cg_scalars[S_ALPHA].
+  Half<P> cg_r = {nullptr, nullptr};
+  CHalf<P> cg_p = {nullptr, nullptr};
+  Half<typename IncrementPrec<P>::type> cg_x = {nullptr, nullptr};  // solution increment
+  const double* cg_scalars = nullptr;
 };
 
 struct LaunchCfg {

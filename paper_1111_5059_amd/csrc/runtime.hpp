@@ -65,6 +65,23 @@ struct Geometry {
   }
 };
 
+// Optional per-launch timing of the hop and fifth-dimension kernels: a HIP event
+// pair on the context stream around each launch, aggregated per kernel variant
+// (named as the compiler names the template instance) with its algorithmic bytes.
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // reused across reports
+  size_t used = 0;
+  struct Mark {
+    int cls;
+    size_t e0, e1;
+    double bytes;
+  };
+  std::vector<Mark> marks;
+  std::vector<std::string> names;
+  std::map<std::string, int> ids;
+};
+
 }  // namespace dwf
 
 struct dwf_ctx {
@@ -75,6 +92,7 @@ struct dwf_ctx {
   std::map<std::string, std::pair<void*, size_t>> emats;  // fifth-dimension matrices by key
   std::map<long long, dwf::LaunchCfg> tune;              // (prec, Ls) -> hop launch configuration
   double* h_scalars = nullptr;                           // pinned host mirror of the CG scalars
+  dwf::KernelTimer timer;
 };
 
 namespace dwf {
@@ -85,6 +103,19 @@ LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls);
 // device buffer of the fifth-dimension matrices for one parameter set
 const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec);
 double read_scalar(dwf_ctx* ctx, const double* dscalars, int slot);
+// timer marks around one launch (no-ops while timing is off); begin returns the mark index or -1
+long timer_begin(dwf_ctx* ctx, const std::string& kernel);
+void timer_end(dwf_ctx* ctx, long mark, double bytes);
+std::string timer_report(dwf_ctx* ctx);  // synchronizes; one line per kernel variant; clears the marks
+void timer_release(dwf_ctx* ctx);
+
+// bytes of one 5D site of a spinor field in storage precision P (with the FP16 norm)
+template <typename P>
+constexpr double spinor_site_bytes() { return 12.0 * sizeof(typename P::S) + (P::NORM ? 4.0 : 0.0); }
+inline const char* prec_tag(int id) {
+  static const char* n[4] = {"dwf::P64", "dwf::P32", "dwf::P16", "dwf::PB16"};
+  return n[id & 3];
+}
 
 // slots of the per-parameter fifth-dimension matrix table ([slot][2][Ls][Ls])
 enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_COUNT };
@@ -144,9 +175,22 @@ struct Op {
   long n5() const { return g->nsites * Ls; }
 
   // out(out_par) = ax x + Epi . (scale H [F] in)   (H^dag F^dag ... when dag: no prologue)
+  // CG step fused into a dagger hop (r.data == nullptr: none)
+  struct CgStep {
+    Half<P> r = {nullptr, nullptr};
+    CHalf<P> p = {nullptr, nullptr};
+    Half<typename IncrementPrec<P>::type> x = {nullptr, nullptr};
+    const double* scalars = nullptr;
+  };
+
   void hop(int out_par, CHalf<P> in, Half<P> out, bool dag, bool pro, double scale, const R* epi,
-           CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr) const {
+           CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr,
+           const CgStep& cg = CgStep()) const {
     HopArgs<P> a;
+    a.cg_r = cg.r;
+    a.cg_p = cg.p;
+    a.cg_x = cg.x;
+    a.cg_scalars = cg.scalars;
     a.in = in;
     a.out = out;
     a.links = U[out_par];
@@ -167,12 +211,37 @@ struct Op {
     a.x = x;
     a.ax = R(ax);
     a.norm_partials = partials;
+    long mark = -1;
+    if (ctx->timer.on) mark = timer_begin(ctx, hop_name(a, dag, pro && moebius));
     DWF_CHECK_LAUNCH(launch_hop<P>(a, dag, pro && moebius, cfg, ctx->stream));
+    if (mark >= 0) {
+      // fields read and written once: in, out (or with the CG step: r, p read, r written, the
+      // increment xl read and written), x
+      const double fb = spinor_site_bytes<P>();
+      const double bytes = cg.r.data ? fb * (4 + (x.data ? 1 : 0)) + 2 * spinor_site_bytes<typename IncrementPrec<P>::type>()
+                                     : fb * (2 + (x.data ? 1 : 0));
+      timer_end(ctx, mark, double(n5()) * bytes + double(g->nsites) * 72 * sizeof(S));
+    }
+  }
+  // the template instance launch_hop selects for these arguments (kernel name as demangled)
+  std::string hop_name(const HopArgs<P>& a, bool dag, bool pro) const {
+    const int ls = (Ls == 8 || Ls == 12 || Ls == 16 || Ls == 32) ? Ls : 0;
+    int epi = 0;
+    if (a.E) epi = (a.epi_scan && cfg.ns == 1 && (ls == 8 || ls == 16 || ls == 32)) ? 2 : 1;
+    return std::string("hop_kernel<") + prec_tag(P::ID) + ", " + std::to_string(ls) + ", " + std::to_string(cfg.ns) +
+           ", " + (dag ? "true" : "false") + ", " + (pro ? "true" : "false") + ", " + std::to_string(epi) + ", " +
+           (cfg.ll ? "true" : "false") + ", " + (a.cg_r.data ? "true" : "false") + ">";
   }
   void fifth(CHalf<P> in, Half<P> out, int slot, CHalf<P> x = {nullptr, nullptr}, double ax = 0.0,
              double* partials = nullptr) const {
+    long mark = -1;
+    if (ctx->timer.on) {
+      const int seg = (scan_ok && (Ls == 8 || Ls == 16 || Ls == 32)) ? Ls : 0;
+      mark = timer_begin(ctx, std::string("fifth_kernel<") + prec_tag(P::ID) + ", " + std::to_string(seg) + ">");
+    }
     DWF_CHECK_LAUNCH(launch_fifth<P>(in, out, em(slot), scan_ok ? &es[slot] : nullptr, x, R(ax), g->nsites, Ls,
                                      partials, ctx->stream));
+    if (mark >= 0) timer_end(ctx, mark, double(n5()) * spinor_site_bytes<P>() * (x.data ? 3 : 2));
   }
   // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd)
   void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {
@@ -184,6 +253,20 @@ struct Op {
     fifth(in, tmp_o, E_AINVDAG);
     hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
     hop(1, cv(tmp_e), out, true, false, -0.25, moebius ? em(E_FDAG) : nullptr, in, 1.0, partials);
+  }
+  // M_prec^dag q with the CG step fused into its last hop: r -= alpha M_prec^dag q,
+  // xl += alpha p, per-workgroup partials of |r|^2 (alpha read from scalars on the device)
+  void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, CHalf<P> p,
+                    Half<typename IncrementPrec<P>::type> xl, const double* scalars, double* partials) const {
+    fifth(in, tmp_o, E_AINVDAG);
+    hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
+    CgStep cg;
+    cg.r = r;
+    cg.p = p;
+    cg.x = xl;
+    cg.scalars = scalars;
+    hop(1, cv(tmp_e), Half<P>{nullptr, nullptr}, true, false, -0.25, moebius ? em(E_FDAG) : nullptr, in, 1.0, partials,
+        cg);
   }
   // full D (or D^dag):  (D psi)_p = A psi_p - 1/2 H F psi_{1-p};  (D^dag psi)_p = A^dag psi_p - 1/2 F^dag H^dag psi_{1-p}
   void full(CHalf<P> in_e, CHalf<P> in_o, Half<P> out_e, Half<P> out_o, bool dag) const {

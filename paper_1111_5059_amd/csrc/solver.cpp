@@ -69,7 +69,8 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   double* sc = scalars_buf(ctx);
   hipStream_t s = ctx->stream;
   constexpr bool MIXED = !std::is_same<Pi, P64>::value;
-  using PX = typename std::conditional<MIXED, P32, P64>::type;
+  // solution increment between reliable updates (FP32, or FP64 for FP64 iterations)
+  using PX = typename IncrementPrec<Pi>::type;
   constexpr bool RESTART = std::is_same<Pi, PB16>::value;
 
   // FP64 residual r_hi = rhs - M^dag M x
@@ -98,7 +99,6 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   if (!MIXED) r = hview<Pi>((void*)rhi.data, g, Ls);
   Half<Pi> p = hview<Pi>(ws_get(ctx, tag + ".p." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> q = hview<Pi>(ws_get(ctx, tag + ".q." + pname(Pi::ID), hbi), g, Ls);
-  Half<Pi> Ap = hview<Pi>(ws_get(ctx, tag + ".Ap." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> te = hview<Pi>(ws_get(ctx, tag + ".te." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> to = hview<Pi>(ws_get(ctx, tag + ".to." + pname(Pi::ID), hbi), g, Ls);
   Half<PX> xl = hview<PX>(MIXED ? ws_get(ctx, tag + ".xlo", half_size<PX>(g, Ls)) : (void*)x.data, g, Ls);
@@ -111,15 +111,14 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   DWF_CHECK_LAUNCH(launch_set_scalar(sc, S_RR, rr, s));
   double rr_max = rr, rr_true = rr;
   const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
-  const int nb_red = reduction_blocks(n5);
   int it = 0;
   while (it < maxit) {
     // q = M p, |q|^2 -> alpha = rr / |q|^2
     opi.mprec(cv(p), q, te, part);
     DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_QQ, 1, s));
-    opi.mprec_dag(cv(q), Ap, to, te);
-    DWF_CHECK_LAUNCH((launch_cg_update<Pi, PX>(xl, cv(p), r, cv(Ap), sc, n5, Ls, part, s)));
-    DWF_CHECK_LAUNCH(launch_reduce(part, nb_red, 1, sc, S_RRNEW, 0, s));
+    // r -= alpha M^dag q, xl += alpha p, |r|^2, fused into the last hop of M^dag q
+    opi.mprec_dag_cg(cv(q), to, te, r, cv(p), xl, sc, part);
+    DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_RRNEW, 0, s));
     double rr_new = read_scalar(ctx, sc, S_RRNEW);
     ++it;
     if (!std::isfinite(rr_new)) throw Error{DWF_ERR_NAN, "non-finite residual in CG iteration"};

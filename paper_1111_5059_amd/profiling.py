@@ -2,12 +2,13 @@
 
 python -m paper_1111_5059_amd.profiling stats  <run_kernel_stats.csv> <kernel-substring> [command]
 python -m paper_1111_5059_amd.profiling traffic <fetch_counter_collection.csv> <write_counter_collection.csv>
-        <kernel-substring> <copy-bytes> <out.json>
+        <copy-bytes> <out.json>
 
-``traffic`` converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the named kernel into HBM
-bytes per launch, each scaled by what the same counter reads for a plain device copy of a
-known size (the largest copy kernel in the same run), and records the hash of the kernel
-sources so that a later kernel change invalidates the figure.
+``traffic`` converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every hop and
+fifth-dimension kernel variant in the run into HBM bytes per launch, each scaled by what the
+same counter reads for a plain device copy of a known size (the largest copy kernel in the
+same run), and records the hash of the kernel sources so that a later kernel change
+invalidates the figures.
 """
 import csv
 import json
@@ -52,6 +53,35 @@ def counter_per_dispatch(path, kernel_substring, counter):
     return vals, grids
 
 
+FAMILIES = ("hop_kernel<", "fifth_kernel<")
+
+
+def short_name(full):
+    """template instance of a hop / fifth-dimension kernel, without namespace and arguments"""
+    for fam in FAMILIES:
+        i = full.find(fam)
+        if i < 0:
+            continue
+        depth, j = 0, i + len(fam) - 1
+        while j < len(full):
+            depth += {"<": 1, ">": -1}.get(full[j], 0)
+            if depth == 0:
+                return full[i:j + 1]
+            j += 1
+    return None
+
+
+def per_kernel(path, counter):
+    out = {}
+    for r in _rows(path):
+        if _col(r, "Counter_Name") != counter:
+            continue
+        k = short_name(_col(r, "Kernel_Name"))
+        if k is not None:
+            out.setdefault(k, []).append(float(_col(r, "Counter_Value")))
+    return out
+
+
 def copy_counter(path, counter):
     """counter of the largest device copy in the run (torch's copy kernel)"""
     best = None
@@ -72,20 +102,23 @@ def main(argv):
             print(json.dumps(k))
         return
     if argv[0] == "traffic":
-        fetch_csv, write_csv, ksub, copy_bytes, out = argv[1], argv[2], argv[3], int(argv[4]), argv[5]
-        f, _ = counter_per_dispatch(fetch_csv, ksub, "FETCH_SIZE")
-        w, _ = counter_per_dispatch(write_csv, ksub, "WRITE_SIZE")
+        fetch_csv, write_csv, copy_bytes, out = argv[1], argv[2], int(argv[3]), argv[4]
+        f = per_kernel(fetch_csv, "FETCH_SIZE")
+        w = per_kernel(write_csv, "WRITE_SIZE")
         cf = copy_counter(fetch_csv, "FETCH_SIZE")
         cw = copy_counter(write_csv, "WRITE_SIZE")
         fscale = copy_bytes / (cf[1] * 1024.0)
         wscale = copy_bytes / (cw[1] * 1024.0)
-        fetch = sum(f) / len(f) * 1024.0 * fscale
-        write = sum(w) / len(w) * 1024.0 * wscale
+        kernels = {}
+        for k in sorted(set(f) & set(w)):
+            fetch = sum(f[k]) / len(f[k]) * 1024.0 * fscale
+            write = sum(w[k]) / len(w[k]) * 1024.0 * wscale
+            kernels[k] = {"dispatches": len(f[k]), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+                          "hbm_bytes_per_launch": fetch + write}
         sys.path.insert(0, ROOT)
         import bench
-        d = {"kernel": ksub, "dispatches": len(f), "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-             "hbm_bytes_per_launch": fetch + write, "copy_kernel": cf[2][:120], "copy_bytes": copy_bytes,
-             "fetch_scale": fscale, "write_scale": wscale, "kernel_source_sha256_16": bench.kernel_source_hash()}
+        d = {"copy_kernel": cf[2][:120], "copy_bytes": copy_bytes, "fetch_scale": fscale, "write_scale": wscale,
+             "kernel_source_sha256_16": bench.kernel_source_hash(), "kernels": kernels}
         with open(out, "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d))

@@ -163,3 +163,44 @@ def test_pack_roundtrip_and_errors(env):
     src = lat.pack(psi)
     with pytest.raises(dwf.DwfError):
         dwf.dwf_dslash(ctx, lat.params(), src, src, src, dwf.OP_HOP, 0, False)
+
+
+def test_kernel_timing_report(env):
+    """Per-launch HIP-event timing: one record per hop / fifth-dimension launch, named as the
+    template instance the dispatcher selects, with the algorithmic bytes of each launch."""
+    dwf, ctx = env
+    dims, Ls = (8, 8, 8, 8), 16
+    U, psi = make(dims, Ls, 810)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.02)
+    P = dwf.FP16
+    Ug = lat.pack_gauge(U, P)
+    src = lat.pack(mask(psi, dims, 1), dwf.KIND_ODD, P)
+    dst = lat.empty(dwf.KIND_ODD, P)
+    dwf.dwf_timing_report(ctx)  # discard earlier records
+    dwf.dwf_timing_enable(ctx, True)
+    try:
+        dwf.dwf_dslash(ctx, lat.params(P), Ug, src, dst, dwf.OP_MPREC, 1, False)
+        dwf.dwf_dslash(ctx, lat.params(P), Ug, src, dst, dwf.OP_MPREC, 1, True)
+        rep = dwf.dwf_timing_report(ctx)
+    finally:
+        dwf.dwf_timing_enable(ctx, False)
+    spb, ns, xcd, ll = dwf.dwf_tune_get(ctx, P, Ls)
+    llb = "true" if ll else "false"
+    epi = 2 if ns == 1 else 1
+    nsites = 8 ** 4 // 2
+    site = 12 * 4 + 4  # FP16 spinor (12 half2) + FP32 norm per 5D site
+    links = nsites * 72 * 4
+    want = {
+        # M_prec: two hops with the A^-1 epilogue, the second with the axpy operand
+        f"hop_kernel<dwf::P16, 16, {ns}, false, false, {epi}, {llb}, false>": (2, nsites * Ls * site * 5 + 2 * links),
+        # M_prec^dag: A^-dag, then a dagger hop with an epilogue and one without
+        f"hop_kernel<dwf::P16, 16, {ns}, true, false, {epi}, {llb}, false>": (1, nsites * Ls * site * 2 + links),
+        f"hop_kernel<dwf::P16, 16, {ns}, true, false, 0, {llb}, false>": (1, nsites * Ls * site * 3 + links),
+        "fifth_kernel<dwf::P16, 16>": (1, nsites * Ls * site * 2),
+    }
+    assert set(rep) == set(want), rep
+    for k, (n, nbytes) in want.items():
+        assert rep[k]["launches"] == n, k
+        assert rep[k]["bytes"] == pytest.approx(nbytes, rel=1e-12), k
+        assert rep[k]["ms"] > 0.0
+    assert dwf.dwf_timing_report(ctx) == {}
