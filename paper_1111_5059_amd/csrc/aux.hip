@@ -240,6 +240,62 @@ int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, doubl
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// p_out = r + beta p_in and fp = (fb + fc S~) p_out: the p update of CG with the Moebius input
+// factor F = b + c S~ applied to the new direction, so that the hops of M p need no prologue.
+// Each thread forms the new p on its slice and on the two neighbouring slices F reads (upper
+// spins of s-1, lower spins of s+1; -m at the ends); p_in and p_out are different buffers.
+template <typename P>
+__global__ void __launch_bounds__(256) cg_pupdate_f_kernel(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp,
+                                                            double beta, double* scalars, double rr_new, long n5,
+                                                            int Ls, double fb, double fc, double fm) {
+  using R = typename P::R;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) scalars[S_RR] = rr_new;
+  if (i >= n5) return;
+  const long xs = i / Ls;
+  const int s = int(i - xs * Ls);
+  int su = s - 1, sl = s + 1;
+  R fu = R(fc), fl = R(fc);
+  if (su < 0) { su = Ls - 1; fu = R(-fc * fm); }
+  if (sl >= Ls) { sl = 0; fl = R(-fc * fm); }
+  cx<R> v[12], up[6], lo[6];
+  load_spinor<P>(r, xs, s, Ls, v);
+  load_half_spinor<P>(r, xs, su, Ls, 0, up);
+  load_half_spinor<P>(r, xs, sl, Ls, 6, lo);
+  if (beta != 0.0) {
+    cx<R> pv[12], pu[6], pl[6];
+    load_spinor<P>(pin, xs, s, Ls, pv);
+    load_half_spinor<P>(pin, xs, su, Ls, 0, pu);
+    load_half_spinor<P>(pin, xs, sl, Ls, 6, pl);
+    const R b = R(beta);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = v[k] + b * pv[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      up[k] = up[k] + b * pu[k];
+      lo[k] = lo[k] + b * pl[k];
+    }
+  }
+  store_spinor<P>(pout, xs, s, Ls, v);
+  cx<R> f[12];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    f[k] = R(fb) * v[k] + fu * up[k];
+    f[6 + k] = R(fb) * v[6 + k] + fl * lo[k];
+  }
+  store_spinor<P>(fp, xs, s, Ls, f);
+}
+
+template <typename P>
+int launch_cg_pupdate_f(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp, double beta, double* scalars,
+                        double rr_new, long n5, int Ls, double b, double c, double m, hipStream_t st) {
+  if (n5 <= 0) return 0;
+  if (pin.data == pout.data || (beta != 0.0 && !pin.data)) return -1;
+  hipLaunchKernelGGL((cg_pupdate_f_kernel<P>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, r, pin, pout,
+                     fp, beta, scalars, rr_new, n5, Ls, b, c, m);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // Domain-wall <-> overlap basis change on a half field (site-local):
 //   (P^-1 x)_s = P- x_s + P+ x_{s-1 mod Ls},   (P y)_s = P- y_s + P+ y_{s+1 mod Ls}
 // P+ = spins 0,1 (components 0..5), P- = spins 2,3 (components 6..11).
@@ -424,6 +480,8 @@ int launch_convert_links(const typename Pi::S* in, typename Po::S* out, long n, 
   template int launch_dot<P>(CHalf<P>, CHalf<P>, long, int, double*, hipStream_t);                               \
   template int launch_axpby<P>(double, CHalf<P>, double, Half<P>, long, int, hipStream_t);                        \
   template int launch_cg_pupdate<P>(CHalf<P>, Half<P>, double, double*, double, long, int, hipStream_t);        \
+  template int launch_cg_pupdate_f<P>(CHalf<P>, CHalf<P>, Half<P>, Half<P>, double, double*, double, long, int,   \
+                                      double, double, double, hipStream_t);                                     \
   template int launch_pack_gauge<P>(const GeomTables&, const double2*, P::S*, hipStream_t);                      \
   template int launch_pack_half<P>(const GeomTables&, int, int, const double2*, Half<P>, hipStream_t);           \
   template int launch_unpack_half<P>(const GeomTables&, int, int, CHalf<P>, double2*, hipStream_t);              \

@@ -185,7 +185,9 @@ LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls) {
   LaunchCfg c;
   c.ns = 1;
   c.xcd = 1;
-  c.ll = 1;
+  // links staged in LDS, except FP16: its links are read by every lane of a site at one
+  // address (a broadcast) and the two staged forms would double the LDS footprint
+  c.ll = prec == DWF_FP16 ? 0 : 1;
   int spb = 256 / Ls;
   if (spb < 1) spb = 1;
   while (spb > 1 && (spb * Ls) % 64 != 0) --spb;
@@ -258,6 +260,7 @@ bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, Fifth
       case E_F: q.a1 = b; q.b1 = c; q.d1 = dS; break;
       case E_FDAG: q.a1 = b; q.b1 = c; q.d1 = -dS; break;
       case E_AINVDAG_FDAG: q.a1 = b; q.b1 = c; q.d1 = -dS; q.has_inv = 1; q.d2 = -dS; break;
+      case E_AINV_F: q.a1 = b; q.b1 = c; q.d1 = dS; q.has_inv = 1; q.d2 = dS; break;
       default: return false;
     }
     e.ch[ch] = q;
@@ -294,8 +297,8 @@ const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, 
       coef *= -z;
     }
     const std::vector<double> Adag = transpose(A, n), Ainvdag = transpose(Ainv, n), Fdag = transpose(F, n);
-    const std::vector<double> AinvdagFdag = matmul(Ainvdag, Fdag, n);
-    const std::vector<double>* mats[E_COUNT] = {&A, &Adag, &Ainv, &Ainvdag, &F, &Fdag, &AinvdagFdag};
+    const std::vector<double> AinvdagFdag = matmul(Ainvdag, Fdag, n), AinvF = matmul(Ainv, F, n);
+    const std::vector<double>* mats[E_COUNT] = {&A, &Adag, &Ainv, &Ainvdag, &F, &Fdag, &AinvdagFdag, &AinvF};
     for (int e = 0; e < E_COUNT; ++e)
       std::memcpy(&table[(size_t(e) * 2 + ch) * n * n], mats[e]->data(), sizeof(double) * n * n);
   }

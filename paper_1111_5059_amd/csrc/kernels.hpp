@@ -92,6 +92,10 @@ int launch_cg_update(Half<Px> x, CHalf<P> p, Half<P> r, CHalf<P> Ap, const doubl
 template <typename P>
 int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, double rr_new, long n5, int Ls,
                       hipStream_t st);
+// p_out = r + beta p_in (p_in unused when beta = 0) and fp = (b + c S~) p_out, rr_new -> S_RR
+template <typename P>
+int launch_cg_pupdate_f(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp, double beta, double* scalars,
+                        double rr_new, long n5, int Ls, double b, double c, double m, hipStream_t st);
 // P / P^-1 of the domain-wall <-> overlap transformation on an FP64 half field
 int launch_pshift(CHalf<P64> in, Half<P64> out, int inverse, long nsites, int Ls, hipStream_t st);
 // out(s_out) = scale * in(s_in) on FP64 half fields of extents Ls_in, Ls_out

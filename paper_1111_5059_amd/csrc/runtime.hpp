@@ -118,7 +118,8 @@ inline const char* prec_tag(int id) {
 }
 
 // slots of the per-parameter fifth-dimension matrix table ([slot][2][Ls][Ls])
-enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_COUNT };
+// (A^-1 F = F A^-1: per chirality both are functions of the same shift)
+enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_AINV_F, E_COUNT };
 bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, FifthScan<double>* out);
 
 template <typename P>
@@ -247,6 +248,12 @@ struct Op {
   void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {
     hop(0, in, tmp_e, false, true, 1.0, em(E_AINV));
     hop(1, cv(tmp_e), out, false, true, -0.25, em(E_AINV), in, 1.0, partials);
+  }
+  // M_prec psi from fpsi = F psi prepared by the caller (the CG p update): both hops without
+  // the input factor, the first with the epilogue A^-1 F = F A^-1 (Moebius operators)
+  void mprec_pre(CHalf<P> fin, CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {
+    hop(0, fin, tmp_e, false, false, 1.0, em(E_AINV_F));
+    hop(1, cv(tmp_e), out, false, false, -0.25, em(E_AINV), in, 1.0, partials);
   }
   // M_prec^dag psi = psi - 1/4 F^dag H^dag_oe (A^-dag F^dag) H^dag_eo A^-dag psi
   void mprec_dag(CHalf<P> in, Half<P> out, Half<P> tmp_o, Half<P> tmp_e, double* partials = nullptr) const {

@@ -106,15 +106,28 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
     DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
     DWF_CHECK_LAUNCH(launch_zero(xl.data, half_size<PX>(g, Ls), s));
   }
+  // Moebius operators: the p update also forms F p (two p buffers), and M p runs without
+  // the input factor in its hops
+  const bool PRE = opi.moebius;
+  Half<Pi> p2 = PRE ? hview<Pi>(ws_get(ctx, tag + ".p2." + pname(Pi::ID), hbi), g, Ls) : Half<Pi>{nullptr, nullptr};
+  Half<Pi> fp = PRE ? hview<Pi>(ws_get(ctx, tag + ".fp." + pname(Pi::ID), hbi), g, Ls) : Half<Pi>{nullptr, nullptr};
+  auto p_update = [&](double beta, double rr_new) {
+    if (PRE) {
+      DWF_CHECK_LAUNCH(launch_cg_pupdate_f<Pi>(cv(r), cv(p), p2, fp, beta, sc, rr_new, n5, Ls, opi.b, opi.c, opi.m, s));
+      std::swap(p, p2);
+    } else {
+      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, beta, sc, rr_new, n5, Ls, s));
+    }
+  };
   // p = r
-  DWF_CHECK_LAUNCH(launch_axpby<Pi>(1.0, cv(r), 0.0, p, n5, Ls, s));
-  DWF_CHECK_LAUNCH(launch_set_scalar(sc, S_RR, rr, s));
+  p_update(0.0, rr);
   double rr_max = rr, rr_true = rr;
   const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
   int it = 0;
   while (it < maxit) {
     // q = M p, |q|^2 -> alpha = rr / |q|^2
-    opi.mprec(cv(p), q, te, part);
+    if (PRE) opi.mprec_pre(cv(fp), cv(p), q, te, part);
+    else opi.mprec(cv(p), q, te, part);
     DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_QQ, 1, s));
     // r -= alpha M^dag q, xl += alpha p, |r|^2, fused into the last hop of M^dag q
     opi.mprec_dag_cg(cv(q), to, te, r, cv(p), xl, sc, part);
@@ -137,7 +150,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
       if (rr_new > target && (RESTART || diverging)) {
         // BF16 (8-bit mantissa): the retained direction loses conjugacy and CG stagnates;
         // restart the Krylov space from the recomputed residual.
-        DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, 0.0, sc, rr_new, n5, Ls, s));
+        p_update(0.0, rr_new);
         rr = rr_new;
         continue;
       }
@@ -147,7 +160,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
       break;
     }
     const double beta = rr_new / rr;
-    DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, beta, sc, rr_new, n5, Ls, s));
+    p_update(beta, rr_new);
     rr = rr_new;
     if (rr > rr_max) rr_max = rr;
   }

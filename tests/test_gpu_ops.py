@@ -204,3 +204,56 @@ def test_kernel_timing_report(env):
         assert rep[k]["bytes"] == pytest.approx(nbytes, rel=1e-12), k
         assert rep[k]["ms"] > 0.0
     assert dwf.dwf_timing_report(ctx) == {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+def test_every_launch_shape_gives_the_same_operator(env, ora, prec):
+    """Every launch shape the autotuner may install (sites per workgroup, s-slices per thread,
+    XCD-aware order, links staged in LDS) gives M_prec and M_prec^dag to the precision's
+    tolerance against the oracle (Moebius operator, ragged last workgroup)."""
+    from paper_1111_5059_amd import autotune
+    dwf, ctx = env
+    P = dwf.PREC_NAMES[prec]
+    dims, Ls = (6, 4, 6, 10), 16
+    U, psi = make(dims, Ls, 820)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.05, b=1.5, c=0.5, tbc=1)
+    Ug = lat.pack_gauge(U, P)
+    po = ora.params(dims, Ls, mass=0.05, b=1.5, c=0.5, tbc=1)
+    psio = mask(psi, dims, 1)
+    src = lat.pack(psio, dwf.KIND_ODD, P)
+    refs = {dag: ora.mprec(po, U, psio, dagger=dag) for dag in (False, True)}
+    tried = 0
+    try:
+        for c in autotune.candidates(P, Ls):
+            try:
+                dwf.dwf_tune_set(ctx, P, Ls, c["spb"], c["ns"], c["xcd"], c["ll"])
+            except dwf.DwfError:
+                continue  # a shape the kernel cannot run is rejected before launch
+            tried += 1
+            for dag in (False, True):
+                dst = lat.empty(dwf.KIND_ODD, P)
+                dwf.mobius_dslash(ctx, lat.params(P), Ug, src, dst, dwf.OP_MPREC, 1, dag)
+                err = rel_err(lat.unpack_np(dst, dwf.KIND_ODD, P), refs[dag])
+                assert err < PREC_TOL[prec], (c, dag, err)
+    finally:
+        dwf.dwf_tune_set(ctx, P, Ls, 0, 0)
+    assert tried >= 8
+
+
+def test_autotuner_installs_the_fastest_shape(env, tmp_path):
+    from paper_1111_5059_amd import autotune
+    dwf, ctx = env
+    dims, Ls = (8, 8, 8, 8), 8
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.05)
+    U64 = lat.pack_gauge(synth.random_links(dims, 0.5, 830))
+    cache = str(tmp_path / "tune.json")
+    shapes = [{"spb": 8, "ns": 1, "xcd": 1, "ll": 1}, {"spb": 16, "ns": 2, "xcd": 0, "ll": 0}]
+    try:
+        best, ms, table = autotune.tune_hop(lat, U64, "fp32", reps=2, cache=cache, shapes=shapes)
+        assert len(table) == 2 and ms == min(r["ms"] for r in table)
+        assert autotune.current(lat, "fp32") == best
+        dwf.dwf_tune_set(ctx, dwf.FP32, Ls, 0, 0)
+        assert autotune.load(lat, "fp32", cache) == dict(best, ms=ms)
+        assert autotune.current(lat, "fp32") == best
+    finally:
+        dwf.dwf_tune_set(ctx, dwf.FP32, Ls, 0, 0)
