@@ -118,27 +118,24 @@ def time_hop(dwf, ctx, lat, U64, prec, reps=20):
             "GFLOPs": 1320.0 * nsites / (ms * 1e-3) / 1e9}
 
 
-def apply_operators(dwf, ctx, lat, inner, U64, prec, reps=5):
-    """M_prec and M_prec^dag of the target (DWF) and inner (Moebius) operators in storage
-    precision prec: launches every hop / fifth-dimension kernel variant of the solves."""
+def apply_operators(dwf, ctx, lat, inner, U64, bg, prec, iters=4):
+    """A few iterations of the mixed-precision CG of the target (DWF) and inner (Moebius)
+    systems in storage precision prec: launches every hop / fifth-dimension kernel variant
+    of the solves (for the hardware-counter runs)."""
     import torch
     P = dwf.PREC_NAMES[prec]
-    Ug = lat.empty(dwf.KIND_GAUGE, P)
-    dwf.dwf_convert(ctx, lat.params(P), dwf.KIND_GAUGE, dwf.FP64, U64, P, Ug)
-    for lt, fn in ((lat, dwf.dwf_dslash), (inner, dwf.mobius_dslash)):
-        tmp = lt.zeros(dwf.KIND_ODD, dwf.FP64)
-        rng = torch.Generator(device="cuda")
-        rng.manual_seed(11)
-        tmp.view(torch.float64).normal_(generator=rng)
-        a = lt.empty(dwf.KIND_ODD, P)
-        dwf.dwf_convert(ctx, lt.params(P), dwf.KIND_ODD, dwf.FP64, tmp, P, a)
-        bb = lt.empty(dwf.KIND_ODD, P)
-        p = lt.params(P)
-        for _ in range(reps):
-            fn(ctx, p, Ug, a, bb, dwf.OP_MPREC, 0, False)
-            fn(ctx, p, Ug, bb, a, dwf.OP_MPREC, 0, True)
+    for lt in (lat, inner):
+        x = lt.zeros(dwf.KIND_FULL)
+        if lt is lat:
+            b = bg
+        else:  # a Gaussian source on the inner lattice's fifth-dimension extent
+            b = lt.zeros(dwf.KIND_FULL)
+            rng = torch.Generator(device="cuda")
+            rng.manual_seed(11)
+            b.view(torch.float64).normal_(generator=rng)
+        dwf.cg_ne(ctx, lt.params(prec_inner=P), U64, b, x, tol=1e-14, maxit=iters)
         torch.cuda.synchronize()
-        del tmp, a, bb
+        del x, b
 
 
 def cpu_baseline(workload, U, b_nat, fp64_iters, seconds_budget=25.0):
@@ -225,7 +222,7 @@ def main():
     if args.only_hop:
         # the operator kernels of the solves, then a plain device copy of known size
         # (calibrates FETCH_SIZE / WRITE_SIZE per byte)
-        apply_operators(dwf, ctx, lat, inner, U64, args.inner)
+        apply_operators(dwf, ctx, lat, inner, U64, bg, args.inner)
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         a.fill_(1)
         c = torch.empty_like(a)

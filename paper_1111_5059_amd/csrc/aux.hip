@@ -63,13 +63,23 @@ __global__ void __launch_bounds__(RED_THREADS) dot_kernel(CHalf<P> a, CHalf<P> b
   }
 }
 
-__global__ void __launch_bounds__(256) reduce_kernel(const double* partials, int n, int ncomp, double* scalars,
-                                                      int slot, int mode) {
+// One workgroup of 1024 threads; each thread keeps four independent partial sums (loads in
+// flight) over a fixed set of indices, combined in a fixed order: deterministic.
+__global__ void __launch_bounds__(1024) reduce_kernel(const double* partials, int n, int ncomp, double* scalars,
+                                                       int slot, int mode) {
   __shared__ double red[16];
   for (int c = 0; c < ncomp; ++c) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i * ncomp + c];
-    const double t = block_sum(acc, red);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int stride = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+      a0 += partials[i * ncomp + c];
+      a1 += partials[(i + stride) * ncomp + c];
+      a2 += partials[(i + 2 * stride) * ncomp + c];
+      a3 += partials[(i + 3 * stride) * ncomp + c];
+    }
+    for (; i < n; i += stride) a0 += partials[i * ncomp + c];
+    const double t = block_sum((a0 + a1) + (a2 + a3), red);
     __syncthreads();
     if (threadIdx.x == 0) {
       scalars[slot + c] = t;
@@ -86,7 +96,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(const double* partials, int
 }
 
 int launch_reduce(const double* partials, int n, int ncomp, double* scalars, int slot, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, partials, n, ncomp, scalars, slot, mode);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, partials, n, ncomp, scalars, slot, mode);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

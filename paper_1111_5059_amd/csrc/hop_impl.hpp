@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
   }
-  if constexpr (EPI == 2) {
+  if constexpr (EPI >= 2) {
     // recurrence form along s: the site's Ls lanes are one segment of the wave
     static_assert(NS == 1 && LS > 0 && (64 % LS) == 0, "scan epilogue needs one slice per lane");
     fifth_scan_apply<LS>(acc[0], s0, a.es);
@@ -406,6 +406,12 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd
       }
     }
   }
+  if constexpr (EPI == 3 && !CG) {
+    // second output: the site-local operator es2 on the final result (all lanes of a site
+    // are active or inactive together, so the segment shuffles stay within active lanes)
+    fifth_scan_apply<LS>(acc[0], s0, a.es2);
+    if (active) store_spinor<P>(a.out2, x, s0, Ls, acc[0]);
+  }
   if (a.norm_partials) {
     const double t = block_sum(nrm, red);
     if (threadIdx.x == 0) a.norm_partials[blockIdx.x] = t;
@@ -427,13 +433,20 @@ static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t s
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// epilogue: 0 none, 1 dense matrices in LDS, 2 recurrence (scan) form, 3 scan form and a
+// second, scanned output (only where the site's Ls slices form one wave segment)
 template <typename P, int LS, int NS, bool DAG, bool PRO, bool CG>
 static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
-  if (!a.E) return launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st);
+  if (!a.E) return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st);
   if constexpr (NS == 1 && (LS == 8 || LS == 16 || LS == 32)) {
-    if (a.epi_scan) return launch_hop_t<P, LS, NS, DAG, PRO, 2, CG>(a, cfg, st);
+    if (a.epi_scan) {
+      if constexpr (!DAG && !CG) {
+        if (a.out2.data) return launch_hop_t<P, LS, NS, DAG, PRO, 3, CG>(a, cfg, st);
+      }
+      return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 2, CG>(a, cfg, st);
+    }
   }
-  return launch_hop_t<P, LS, NS, DAG, PRO, 1, CG>(a, cfg, st);
+  return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 1, CG>(a, cfg, st);
 }
 
 // the fused CG step exists for the dagger hop only (the last hop of M^dag M)

@@ -42,6 +42,10 @@ struct HopArgs {
   CHalf<P> x;                  // axpy operand (data == nullptr: none)
   typename P::R ax;
   double* norm_partials;       // per-block sum |out|^2 (|cg_r|^2 with the fused CG step) or nullptr
+  // second output (scan epilogue only): out2 = es2 . out, a site-local operator applied to
+  // the final result (out2.data == nullptr: none)
+  Half<P> out2 = {nullptr, nullptr};
+  FifthScan<typename P::R> es2;
   // CG step fused into the last hop of M^dag M p (cg_r.data == nullptr: none).  With it the
   // result v is not stored; instead r -= alpha v and xl += alpha p, alpha = cg_scalars[S_ALPHA].
   Half<P> cg_r = {nullptr, nullptr};

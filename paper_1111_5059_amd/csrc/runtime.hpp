@@ -184,10 +184,13 @@ struct Op {
     const double* scalars = nullptr;
   };
 
+  // out2 (optional): slot2 applied to the final result, a second output of the same launch
   void hop(int out_par, CHalf<P> in, Half<P> out, bool dag, bool pro, double scale, const R* epi,
            CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr,
-           const CgStep& cg = CgStep()) const {
+           const CgStep& cg = CgStep(), Half<P> out2 = {nullptr, nullptr}, int slot2 = 0) const {
     HopArgs<P> a;
+    a.out2 = out2;
+    if (out2.data) a.es2 = es[slot2];
     a.cg_r = cg.r;
     a.cg_p = cg.p;
     a.cg_x = cg.x;
@@ -220,7 +223,7 @@ struct Op {
       // increment xl read and written), x
       const double fb = spinor_site_bytes<P>();
       const double bytes = cg.r.data ? fb * (4 + (x.data ? 1 : 0)) + 2 * spinor_site_bytes<typename IncrementPrec<P>::type>()
-                                     : fb * (2 + (x.data ? 1 : 0));
+                                     : fb * (2 + (x.data ? 1 : 0) + (out2.data ? 1 : 0));
       timer_end(ctx, mark, double(n5()) * bytes + double(g->nsites) * 72 * sizeof(S));
     }
   }
@@ -228,7 +231,7 @@ struct Op {
   std::string hop_name(const HopArgs<P>& a, bool dag, bool pro) const {
     const int ls = (Ls == 8 || Ls == 12 || Ls == 16 || Ls == 32) ? Ls : 0;
     int epi = 0;
-    if (a.E) epi = (a.epi_scan && cfg.ns == 1 && (ls == 8 || ls == 16 || ls == 32)) ? 2 : 1;
+    if (a.E) epi = (a.epi_scan && cfg.ns == 1 && (ls == 8 || ls == 16 || ls == 32)) ? (a.out2.data ? 3 : 2) : 1;
     return std::string("hop_kernel<") + prec_tag(P::ID) + ", " + std::to_string(ls) + ", " + std::to_string(cfg.ns) +
            ", " + (dag ? "true" : "false") + ", " + (pro ? "true" : "false") + ", " + std::to_string(epi) + ", " +
            (cfg.ll ? "true" : "false") + ", " + (a.cg_r.data ? "true" : "false") + ">";
@@ -244,16 +247,21 @@ struct Op {
                                      partials, ctx->stream));
     if (mark >= 0) timer_end(ctx, mark, double(n5()) * spinor_site_bytes<P>() * (x.data ? 3 : 2));
   }
-  // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd)
-  void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {
+  // the scan epilogue can carry a second output (one s-slice per lane, Ls a wave segment)
+  bool second_output_ok() const { return scan_ok && cfg.ns == 1 && (Ls == 8 || Ls == 16 || Ls == 32); }
+  // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd);
+  // ainvdag_out (optional, see second_output_ok): also A^-dag (M_prec psi)
+  void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr,
+             Half<P> ainvdag_out = {nullptr, nullptr}) const {
     hop(0, in, tmp_e, false, true, 1.0, em(E_AINV));
-    hop(1, cv(tmp_e), out, false, true, -0.25, em(E_AINV), in, 1.0, partials);
+    hop(1, cv(tmp_e), out, false, true, -0.25, em(E_AINV), in, 1.0, partials, CgStep(), ainvdag_out, E_AINVDAG);
   }
   // M_prec psi from fpsi = F psi prepared by the caller (the CG p update): both hops without
   // the input factor, the first with the epilogue A^-1 F = F A^-1 (Moebius operators)
-  void mprec_pre(CHalf<P> fin, CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr) const {
+  void mprec_pre(CHalf<P> fin, CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr,
+                 Half<P> ainvdag_out = {nullptr, nullptr}) const {
     hop(0, fin, tmp_e, false, false, 1.0, em(E_AINV_F));
-    hop(1, cv(tmp_e), out, false, false, -0.25, em(E_AINV), in, 1.0, partials);
+    hop(1, cv(tmp_e), out, false, false, -0.25, em(E_AINV), in, 1.0, partials, CgStep(), ainvdag_out, E_AINVDAG);
   }
   // M_prec^dag psi = psi - 1/4 F^dag H^dag_oe (A^-dag F^dag) H^dag_eo A^-dag psi
   void mprec_dag(CHalf<P> in, Half<P> out, Half<P> tmp_o, Half<P> tmp_e, double* partials = nullptr) const {
@@ -263,9 +271,11 @@ struct Op {
   }
   // M_prec^dag q with the CG step fused into its last hop: r -= alpha M_prec^dag q,
   // xl += alpha p, per-workgroup partials of |r|^2 (alpha read from scalars on the device)
+  // (ainvdag_ready: tmp_o already holds A^-dag in, the second output of mprec)
   void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, CHalf<P> p,
-                    Half<typename IncrementPrec<P>::type> xl, const double* scalars, double* partials) const {
-    fifth(in, tmp_o, E_AINVDAG);
+                    Half<typename IncrementPrec<P>::type> xl, const double* scalars, double* partials,
+                    bool ainvdag_ready = false) const {
+    if (!ainvdag_ready) fifth(in, tmp_o, E_AINVDAG);
     hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
     CgStep cg;
     cg.r = r;

@@ -122,15 +122,18 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   // p = r
   p_update(0.0, rr);
   double rr_max = rr, rr_true = rr;
+  const bool OUT2 = opi.second_output_ok();
   const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
   int it = 0;
   while (it < maxit) {
     // q = M p, |q|^2 -> alpha = rr / |q|^2
-    if (PRE) opi.mprec_pre(cv(fp), cv(p), q, te, part);
-    else opi.mprec(cv(p), q, te, part);
+    // (with A^-dag q, the first step of M^dag q, as a second output of the last hop)
+    const Half<Pi> q2 = OUT2 ? to : Half<Pi>{nullptr, nullptr};
+    if (PRE) opi.mprec_pre(cv(fp), cv(p), q, te, part, q2);
+    else opi.mprec(cv(p), q, te, part, q2);
     DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_QQ, 1, s));
     // r -= alpha M^dag q, xl += alpha p, |r|^2, fused into the last hop of M^dag q
-    opi.mprec_dag_cg(cv(q), to, te, r, cv(p), xl, sc, part);
+    opi.mprec_dag_cg(cv(q), to, te, r, cv(p), xl, sc, part, OUT2);
     DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_RRNEW, 0, s));
     double rr_new = read_scalar(ctx, sc, S_RRNEW);
     ++it;
