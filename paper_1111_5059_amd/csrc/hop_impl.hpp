@@ -250,8 +250,13 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, cons
   }
 }
 
+// FP16: at least 5 waves per SIMD (at most 102 VGPRs), since the kernel is bound by memory
+// latency; not with the fused CG step, whose extra operands would then spill
+template <typename P, bool CG>
+constexpr int hop_min_waves() { return std::is_same<P, P16>::value && !CG ? 5 : 1; }
+
 template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG>
-__global__ void __launch_bounds__(256) hop_kernel(HopArgs<P> a, int spb, int xcd) {
+__global__ void __launch_bounds__(256, (hop_min_waves<P, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
