@@ -81,6 +81,7 @@ def lib():
             "ora_madwf": ([P, P, vp, vp, vp, ci, cd, cd, cd, ci, ctypes.POINTER(MadwfInfo)], ci),
             "ora_action": ([P, vp, vp, vp, cd, ci, ctypes.POINTER(ci)], cd),
             "ora_force": ([P, vp, vp, vp, vp], None),
+            "ora_quotient_force": ([P, P, vp, vp, vp, vp, vp, cd, ci, ctypes.POINTER(ci)], cd),
             "ora_mat3_exp": ([vp, vp, ctypes.c_long], None),
             "ora_fg_force": ([P, vp, vp, cd, vp, vp, vp, cd, ci, vp], None),
         }
@@ -281,6 +282,22 @@ def force(p, U, X):
     lib().ora_force(ctypes.byref(p), _ptr(U), _ptr(X), _ptr(F), e.ctypes.data_as(ctypes.c_void_p))
     dims_r = tuple(int(p.dims[k]) for k in (3, 2, 1, 0))
     return F.reshape((4,) + dims_r + (3, 3)), e.reshape((4,) + dims_r + (8,))
+
+
+def quotient_force(pn, pd, U, phi, x0=None, tol=1e-13, maxit=100000):
+    """Hasenbusch quotient action S = phi^dag M_n (M_d^dag M_d)^-1 M_n^dag phi (Sec. 3) and its
+    force; pn / pd carry the numerator / denominator mass.  Returns (S, F, e, X, iters) with
+    F, e shaped as in force()."""
+    U, phi = _c(U), _c(phi)
+    X = np.zeros_like(phi) if x0 is None else _c(x0).copy()
+    V = int(np.prod(pn.dims))
+    F = np.zeros((4, V, 3, 3), np.complex128)
+    e = np.zeros((4, V, 8), np.float64)
+    it = ctypes.c_int(0)
+    S = lib().ora_quotient_force(ctypes.byref(pn), ctypes.byref(pd), _ptr(U), _ptr(phi), _ptr(X), _ptr(F),
+                                 e.ctypes.data_as(ctypes.c_void_p), float(tol), int(maxit), ctypes.byref(it))
+    dims_r = tuple(int(pn.dims[k]) for k in (3, 2, 1, 0))
+    return S, F.reshape((4,) + dims_r + (3, 3)), e.reshape((4,) + dims_r + (8,)), X, it.value
 
 
 def mat3_exp(A):

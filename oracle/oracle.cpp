@@ -781,19 +781,20 @@ double ora_action(const ora_params* p, const cplx* U, const cplx* phi, cplx* X, 
   return dot(phi, X, n).real();
 }
 
-// Fermion force of S = phi^dag (M^dag M)^-1 phi.  Given X = (M^dag M)^-1 phi,
-// computes for every link and generator e_a(S) = d/dw S[exp(w T_a) U_mu(x)] |_{w=0}
-// (Sec. 2: e_a acts on the link as left multiplication by T_a) and writes
-// F_mu(x) = sum_a e_a(S) T_a  into F[mu][i][3][3]; e (optional) gets e[mu][i][a].
-//   dS = -2 Re <Y, dM X>, Y = M X, dM = -A^-1 dB_oe A^-1 B_eo - A^-1 B_oe A^-1 dB_eo
-void ora_force(const ora_params* p, const cplx* U, const cplx* X, cplx* F, double* e_out) {
+// The derivative of the bilinear form -2 Re <Y, M X> (X, Y on odd sites, M = M_prec of p)
+// along every link and generator: e_a = d/dw [-2 Re <Y, M[exp(w T_a) U_mu(x)] X>] at w = 0
+// (Sec. 2: e_a acts on the link as left multiplication by T_a).  With Y = M X this is
+// e_a(S) of S = phi^dag (M^dag M)^-1 phi, X = (M^dag M)^-1 phi, since dS = -2 Re <Y, dM X>.
+// Writes F_mu(x) = sum_a e_a T_a into F[mu][i][3][3]; e (optional) gets e[mu][i][a].
+//   dM = -A^-1 dB_oe A^-1 B_eo - A^-1 B_oe A^-1 dB_eo
+static void force_xy(const ora_params* p, const cplx* U, const cplx* X, const cplx* Yin, cplx* F, double* e_out) {
   Geom g = geom_of(p);
   const int Ls = p->Ls;
   const long V12 = g.V * 12, n = V12 * Ls;
   EOContext E(p);
-  std::vector<cplx> Y(n), Xe(n), Yo(n), Ye(n), t(n), W(n), Z(n), Xo(X, X + n);
+  std::vector<cplx> Y(Yin, Yin + n), Xe(n), Yo(n), Ye(n), t(n), W(n), Z(n), Xo(X, X + n);
   mask_parity(g, Ls, Xo.data(), 1);
-  mprec(p, E, U, Xo.data(), Y.data(), 0);                     // Y = M X
+  mask_parity(g, Ls, Y.data(), 1);
   apply_B(p, g, U, Xo.data(), t.data(), 0, 0);
   apply_fifth(g, Ls, E.Ainv, t.data(), Xe.data());           // X_e = A^-1 B_eo X
   apply_fifth(g, Ls, E.Ainvdag, Y.data(), Yo.data());        // Y_o' = A^-dag Y
@@ -851,6 +852,44 @@ void ora_force(const ora_params* p, const cplx* U, const cplx* X, cplx* F, doubl
       for (int k = 0; k < 9; ++k) F[((long)mu * g.V + i) * 9 + k] = Fm[k];
     }
   }
+}
+
+// Fermion force of S = phi^dag (M^dag M)^-1 phi given X = (M^dag M)^-1 phi (Y = M X).
+void ora_force(const ora_params* p, const cplx* U, const cplx* X, cplx* F, double* e_out) {
+  Geom g = geom_of(p);
+  const long n = g.V * 12 * p->Ls;
+  EOContext E(p);
+  std::vector<cplx> Xo(X, X + n), Y(n);
+  mask_parity(g, p->Ls, Xo.data(), 1);
+  mprec(p, E, U, Xo.data(), Y.data(), 0);
+  force_xy(p, U, Xo.data(), Y.data(), F, e_out);
+}
+
+// Hasenbusch quotient action (Sec. 3): with a numerator mass pn->mass and a denominator mass
+// pd->mass (same operator otherwise),
+//   S = phi^dag M_n (M_d^dag M_d)^-1 M_n^dag phi,   X = (M_d^dag M_d)^-1 M_n^dag phi,
+//   dS = 2 Re <phi, dM_n X> - 2 Re <Y, dM_d X>,     Y = M_d X,
+// so e_a(S) = e_a[-2 Re <Y, M_d X>] - e_a[-2 Re <phi, M_n X>].  X holds the initial guess on
+// entry and the solution on exit; F and e (optional) as for ora_force.  Returns S.
+double ora_quotient_force(const ora_params* pn, const ora_params* pd, const cplx* U, const cplx* phi, cplx* X,
+                          cplx* F, double* e_out, double tol, int maxit, int* iters) {
+  Geom g = geom_of(pn);
+  const int Ls = pn->Ls;
+  const long n = g.V * 12 * Ls, nl = 4 * g.V;
+  EOContext En(pn), Ed(pd);
+  std::vector<cplx> ph(phi, phi + n), chi(n), Y(n), F2(nl * 9);
+  mask_parity(g, Ls, ph.data(), 1);
+  mprec(pn, En, U, ph.data(), chi.data(), 1);  // chi = M_n^dag phi
+  cg_normal(pd, Ed, U, chi.data(), X, tol, maxit, iters);
+  const double S = dot(chi.data(), X, n).real();
+  mprec(pd, Ed, U, X, Y.data(), 0);  // Y = M_d X
+  std::vector<double> e2(e_out ? nl * 8 : 0);
+  force_xy(pd, U, X, Y.data(), F, e_out);
+  force_xy(pn, U, X, ph.data(), F2.data(), e_out ? e2.data() : nullptr);
+  for (long k = 0; k < nl * 9; ++k) F[k] -= F2[k];
+  if (e_out)
+    for (long k = 0; k < nl * 8; ++k) e_out[k] -= e2[k];
+  return S;
 }
 
 // exp of n 3x3 complex matrices (power series)

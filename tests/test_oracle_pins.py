@@ -434,3 +434,42 @@ def test_mat3_exp_matches_expm(ora):
     E = ora.mat3_exp(A)
     for k in range(20):
         assert np.max(np.abs(E[k] - scipy.linalg.expm(A[k]))) < 1e-12 * np.max(np.abs(E[k]))
+
+
+@pytest.mark.parametrize("bc", [(1.0, 0.0), (1.5, 0.5)])
+def test_quotient_force_finite_difference(ora, bc):
+    """Hasenbusch quotient action of Sec. 3, S = phi^dag M(m_n) (M(m_d)^dag M(m_d))^-1 M(m_n)^dag phi:
+    e_a(S) against central differences of S along exp(+-h T_a) on sampled links."""
+    dims, Ls = (2, 2, 4, 4), 4
+    pn = ora.params(dims, Ls, M5=1.8, mass=0.3, b=bc[0], c=bc[1])
+    pd = ora.params(dims, Ls, M5=1.8, mass=0.05, b=bc[0], c=bc[1])
+    U = synth.random_links(dims, 0.5, 131)
+    phi = synth.gaussian_spinor_parity(dims, Ls, 132, 1)
+    S0, F, e, X, _ = ora.quotient_force(pn, pd, U, phi, tol=1e-14)
+    assert S0 > 0
+    T = ora.generators()
+    h = 1e-4
+    for (mu, t, z, y, x, a) in synth.sample_links(dims, 12, 133):
+        Sp = ora.quotient_force(pn, pd, perturb_link(U, mu, t, z, y, x, scipy.linalg.expm(h * T[a])), phi,
+                                x0=X, tol=1e-14)[0]
+        Sm = ora.quotient_force(pn, pd, perturb_link(U, mu, t, z, y, x, scipy.linalg.expm(-h * T[a])), phi,
+                                x0=X, tol=1e-14)[0]
+        fd = (Sp - Sm) / (2 * h)
+        assert abs(fd - e[mu, t, z, y, x, a]) <= 1e-6 * max(abs(fd), 1e-2)
+    assert np.max(np.abs(F + np.conj(np.swapaxes(F, -1, -2)))) < 1e-12
+    assert np.max(np.abs(np.trace(F, axis1=-2, axis2=-1))) < 1e-12
+
+
+def test_quotient_of_equal_masses_is_constant(ora):
+    """With equal masses M (M^dag M)^-1 M^dag = 1: S = |phi|^2 for every gauge field, so the two
+    force terms cancel (a sign or mass mix-up in either term leaves a force of the size of the
+    one-flavour force)."""
+    dims, Ls = (2, 2, 2, 4), 4
+    p = ora.params(dims, Ls, M5=1.8, mass=0.1, b=1.5, c=0.5)
+    U = synth.random_links(dims, 0.5, 141)
+    phi = synth.gaussian_spinor_parity(dims, Ls, 142, 1)
+    S, F, e, X, _ = ora.quotient_force(p, p, U, phi, tol=1e-14)
+    assert abs(S - np.vdot(phi, phi).real) < 1e-10 * abs(S)
+    _, X1, _ = ora.action(p, U, phi, tol=1e-14)
+    F1, _ = ora.force(p, U, X1)
+    assert np.max(np.abs(F)) < 1e-9 * np.max(np.abs(F1))
