@@ -448,14 +448,18 @@ def test_quotient_force_finite_difference(ora, bc):
     S0, F, e, X, _ = ora.quotient_force(pn, pd, U, phi, tol=1e-14)
     assert S0 > 0
     T = ora.generators()
-    h = 1e-4
+    # fourth-order central differences, h = 1e-3: truncation ~h^4, and the solver's 1e-14
+    # relative accuracy of S contributes about |S| 1e-14 / h
+    h = 1e-3
+
+    def S_at(mu, t, z, y, x, a, w):
+        Uw = perturb_link(U, mu, t, z, y, x, scipy.linalg.expm(w * T[a]))
+        return ora.quotient_force(pn, pd, Uw, phi, x0=X, tol=1e-14)[0]
+
     for (mu, t, z, y, x, a) in synth.sample_links(dims, 12, 133):
-        Sp = ora.quotient_force(pn, pd, perturb_link(U, mu, t, z, y, x, scipy.linalg.expm(h * T[a])), phi,
-                                x0=X, tol=1e-14)[0]
-        Sm = ora.quotient_force(pn, pd, perturb_link(U, mu, t, z, y, x, scipy.linalg.expm(-h * T[a])), phi,
-                                x0=X, tol=1e-14)[0]
-        fd = (Sp - Sm) / (2 * h)
-        assert abs(fd - e[mu, t, z, y, x, a]) <= 1e-6 * max(abs(fd), 1e-2)
+        Sv = {k: S_at(mu, t, z, y, x, a, k * h) for k in (-2, -1, 1, 2)}
+        fd = (8 * (Sv[1] - Sv[-1]) - (Sv[2] - Sv[-2])) / (12 * h)
+        assert abs(fd - e[mu, t, z, y, x, a]) <= 1e-7 * max(abs(fd), 1e-2) + 1e-10 * abs(S0)
     assert np.max(np.abs(F + np.conj(np.swapaxes(F, -1, -2)))) < 1e-12
     assert np.max(np.abs(np.trace(F, axis1=-2, axis2=-1))) < 1e-12
 
