@@ -190,6 +190,23 @@ int mobius_accel_solve(dwf_ctx* ctx, const dwf_params* target, const dwf_params*
 int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U_natural, const void* phi, void* F, double* S,
                   double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
 
+/* Hasenbusch mass ladder (Sec. 3): the quotient actions
+ *   S_i = phi_i^+ M(m_i) (M(m_{i-1})^+ M(m_{i-1}))^-1 M(m_i)^+ phi_i,   i = 1..nq,
+ * M = M_prec of p with its mass replaced by masses[] (nq + 1 entries,
+ * masses[0] < masses[1] < ... < masses[nq]; the paper's m + mu_i, ending at the
+ * Pauli-Villars mass 1).  The nq normal-equation solves (tolerance info->tol,
+ * default 1e-10: Sec. 3 notes they need less than the usual accuracy) run as
+ * one batched CG in p->prec_inner; then F (device, natural force layout,
+ * complex128, out_kind as for fermion_force) receives the sum over i of the
+ * forces e_a(S_i), and S[i] (host, nq entries, may be NULL) the actions.
+ * phi[i]: packed FP64 odd halves.  x_io (may be NULL; entries may be NULL):
+ * X_i = (M(m_{i-1})^+ M(m_{i-1}))^-1 M(m_i)^+ phi_i, initial guess in, solution
+ * out.  Returns DWF_NOT_CONVERGED (F and S still filled) if a solve stopped at
+ * maxit; DWF_ERR_ARG for nq < 1, masses not increasing, NULL pointers. */
+int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* masses, const void* U_natural,
+                   const void* const* phi, void* F, double* S, int out_kind, void* const* x_io,
+                   dwf_solve_info* info);
+
 /* Set / query the launch configuration of the hop kernels for one (precision,
  * Ls): 4D sites per workgroup, s-slices per thread, whether workgroups are
  * remapped so that each XCD walks a contiguous range of the lattice, and

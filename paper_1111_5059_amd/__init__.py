@@ -84,6 +84,8 @@ SIGNATURES = {
     "fermion_force": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(_cd), _cd, _ci, _vp, ctypes.POINTER(SolveInfo)], _ci),
     "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci, _ci, _ci], _ci),
     "dwf_tune_get": ([_vp, _ci, _ci, _ci] + [ctypes.POINTER(_ci)] * 4, _ci),
+    "quotient_force": ([_vp, _PP, _ci, ctypes.POINTER(_cd), _vp, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_cd), _ci,
+                        ctypes.POINTER(_vp), ctypes.POINTER(SolveInfo)], _ci),
     "dwf_timing_enable": ([_vp, _ci], _ci),
     "dwf_timing_report": ([_vp, ctypes.c_char_p, ctypes.c_size_t], _ci),
 }
@@ -233,6 +235,27 @@ def fermion_force(ctx, p, U_natural, phi, F, tau_fg=0.0, out_kind=0, x_io=None, 
                                ctypes.byref(S), float(tau_fg), int(out_kind), _vp(_ptr(x_io)), ctypes.byref(info)))
     d = info.as_dict()
     d["S"] = S.value
+    return d
+
+
+def quotient_force(ctx, p, masses, U_natural, phis, F, out_kind=0, x_io=None, tol=1e-10, delta=0.1,
+                   maxit=100000):
+    """Hasenbusch quotient actions of the mass ladder ``masses`` (Sec. 3) and the sum of their
+    forces into F; returns a dict with the per-quotient actions "S" and the solve statistics."""
+    nq = len(phis)
+    if len(masses) != nq + 1:
+        raise ValueError("masses must hold one more entry than phis")
+    m = (_cd * (nq + 1))(*[float(v) for v in masses])
+    P = (_vp * nq)(*[_ptr(t) for t in phis])
+    X = (_vp * nq)(*[_ptr(t) if t is not None else None for t in x_io]) if x_io is not None else None
+    S = (_cd * nq)()
+    info = SolveInfo()
+    info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
+    rc = _check(lib().quotient_force(ctx.handle, ctypes.byref(p), nq, m, _vp(_ptr(U_natural)), P, _vp(_ptr(F)), S,
+                                     int(out_kind), X, ctypes.byref(info)), allow_not_converged=True)
+    d = info.as_dict()
+    d["S"] = [S[i] for i in range(nq)]
+    d["converged"] = rc == DWF_OK
     return d
 
 

@@ -384,6 +384,24 @@ int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* 
   return guarded([&]() { return dwf::fermion_force(ctx, *p, U, phi, F, S, tau_fg, out_kind, x_io, info); });
 }
 
+int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* masses, const void* U,
+                   const void* const* phi, void* F, double* S, int out_kind, void* const* x_io,
+                   dwf_solve_info* info) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  int rc = check_params(p, true);
+  if (rc) return rc;
+  if (nq < 1 || nq > 64) return fail(DWF_ERR_ARG, "nq must be in 1..64");
+  if (!masses || !U || !phi || !F) return fail(DWF_ERR_ARG, "NULL pointer");
+  for (int i = 0; i < nq; ++i)
+    if (!phi[i]) return fail(DWF_ERR_ARG, "NULL pseudofermion");
+  for (int i = 0; i <= nq; ++i)
+    if (!std::isfinite(masses[i]) || masses[i] < 0.0) return fail(DWF_ERR_ARG, "masses must be finite and >= 0");
+  for (int i = 0; i < nq; ++i)
+    if (!(masses[i] < masses[i + 1])) return fail(DWF_ERR_ARG, "masses must increase along the ladder");
+  if (out_kind != 0 && out_kind != 1) return fail(DWF_ERR_ARG, "out_kind must be 0 or 1");
+  return guarded([&]() { return dwf::quotient_force(ctx, *p, nq, masses, U, phi, F, S, out_kind, x_io, info); });
+}
+
 int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns, int xcd, int ll) {
   if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
   if (kernel_id != 0 || prec < 0 || prec > 3 || Ls < 2 || Ls > 128) return fail(DWF_ERR_ARG, "bad tune key");

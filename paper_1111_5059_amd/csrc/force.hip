@@ -47,6 +47,8 @@ struct ForceArgs {
   long nsites;
   int Ls;
   int kind;
+  double coef;     // F = coef * value (+ F when accumulate)
+  int accumulate;
   double2* F;
 };
 
@@ -108,7 +110,15 @@ __device__ void force_link(const ForceArgs& a, int p, long x) {
       }
   }
 #pragma unroll
-  for (int k = 0; k < 9; ++k) a.F[l * 9 + k] = make_double2(out[k].re, out[k].im);
+  for (int k = 0; k < 9; ++k) {
+    double2 v = make_double2(a.coef * out[k].re, a.coef * out[k].im);
+    if (a.accumulate) {
+      const double2 o = a.F[l * 9 + k];
+      v.x += o.x;
+      v.y += o.y;
+    }
+    a.F[l * 9 + k] = v;
+  }
 }
 
 __global__ void __launch_bounds__(256) force_kernel(ForceArgs a) {
@@ -127,7 +137,8 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs a) {
 }
 
 int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CHalf<P64> Z_e, CHalf<P64> Z_o,
-                 const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st) {
+                 const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st,
+                 double coef, int accumulate) {
   (void)tbc;
   (void)dims;
   ForceArgs a;
@@ -139,6 +150,8 @@ int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CH
   a.nsites = g.nsites;
   a.Ls = Ls;
   a.kind = kind;
+  a.coef = coef;
+  a.accumulate = accumulate;
   a.F = F;
   const long n = 2 * g.nsites * 4;
   hipLaunchKernelGGL(force_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);

@@ -133,8 +133,10 @@ int launch_convert_links(const typename Pi::S* in, typename Po::S* out, long n, 
 // Per link (x, mu) of parity p sites x:  Q = sum_{s,spin} outer products (see force.hip)
 // writes either F = -1/2 TA(M) (kind 0) or the ambient gradient G (kind 1) to the
 // natural force layout.
+// F = coef * value, or F += coef * value with accumulate (one link per thread: no race)
 int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CHalf<P64> Z_e, CHalf<P64> Z_o,
-                 const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st);
+                 const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st,
+                 double coef = 1.0, int accumulate = 0);
 // U' = exp(-eps F) U per link (Cayley-Hamilton exponential), natural layouts
 int launch_fg_update(const double2* F, const double2* U, double eps, double2* Uout, long nlinks, hipStream_t st);
 

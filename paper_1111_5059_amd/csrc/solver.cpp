@@ -732,6 +732,30 @@ int madwf(dwf_ctx* ctx, const dwf_params& pt, const dwf_params& pi, const void* 
 // S = phi^dag (M^dag M)^-1 phi.  X = (M^dag M)^-1 phi (warm start from x_io), Y = M X,
 // X_e = A^-1 B_eo X, Y_o' = A^-dag Y, Y_e' = A^-dag B_oe^dag Y_o', W = F (X, X_e),
 // Z = (Y_e', Y_o'); one thread per link contracts them into F_mu(x) or G_mu(x).
+// The derivative of -2 Re <Y, M X> (X, Y odd half fields, M = M_prec of op) along every link
+// and generator, written as F = sum_a e_a T_a (kind 0) or as the ambient gradient (kind 1):
+// Fout = coef * that (+ Fout with accumulate).
+//   dM = -A^-1 dB_oe A^-1 B_eo - A^-1 B_oe A^-1 dB_eo
+static void force_terms(dwf_ctx* ctx, const Op<P64>& op, const void* Unat, CHalf<P64> X, CHalf<P64> Y, void* Fout,
+                        int kind, double coef, int accumulate) {
+  const Geometry* g = op.g;
+  const int Ls = op.Ls;
+  const size_t hb = half_size<P64>(g, Ls);
+  Half<P64> Xe = hview<P64>(ws_get(ctx, "force.Xe", hb), g, Ls);
+  Half<P64> Zo = hview<P64>(ws_get(ctx, "force.Zo", hb), g, Ls);
+  Half<P64> Ze = hview<P64>(ws_get(ctx, "force.Ze", hb), g, Ls);
+  Half<P64> We = hview<P64>(ws_get(ctx, "force.We", hb), g, Ls);
+  Half<P64> Wo = hview<P64>(ws_get(ctx, "force.Wo", hb), g, Ls);
+  op.hop(0, X, Xe, false, true, -0.5, op.em(E_AINV));                   // X_e = A^-1 B_eo X
+  op.fifth(Y, Zo, E_AINVDAG);                                           // Y_o' = A^-dag Y
+  op.hop(0, cv(Zo), Ze, true, false, -0.5, op.em(E_AINVDAG_FDAG));      // Y_e' = A^-dag B_oe^dag Y_o'
+  op.fifth(X, Wo, E_F);                                                 // W_o = F X
+  op.fifth(cv(Xe), We, E_F);                                            // W_e = F X_e
+  DWF_CHECK_LAUNCH(launch_force(g->tables(), Ls, cv(We), cv(Wo), cv(Ze), cv(Zo),
+                                reinterpret_cast<const double2*>(Unat), g->tbc, g->dims, kind,
+                                reinterpret_cast<double2*>(Fout), ctx->stream, coef, accumulate));
+}
+
 static double force_at(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const void* phi, void* X, void* Fout,
                        int kind, double tol_n, int maxit, double delta, SolveStats* st) {
   const Geometry* g = geometry(ctx, p.dims, p.tbc);
@@ -752,21 +776,9 @@ static double force_at(dwf_ctx* ctx, const dwf_params& p, const void* Unat, cons
   DWF_CHECK_LAUNCH(launch_reduce(part, reduction_blocks(g->nsites * Ls), 2, sc, S_TMP1, 0, s));
   const double S = read_scalar(ctx, sc, S_TMP1);
   Half<P64> Y = hview<P64>(ws_get(ctx, "force.Y", hb), g, Ls);
-  Half<P64> Xe = hview<P64>(ws_get(ctx, "force.Xe", hb), g, Ls);
-  Half<P64> Zo = hview<P64>(ws_get(ctx, "force.Zo", hb), g, Ls);
-  Half<P64> Ze = hview<P64>(ws_get(ctx, "force.Ze", hb), g, Ls);
-  Half<P64> We = hview<P64>(ws_get(ctx, "force.We", hb), g, Ls);
-  Half<P64> Wo = hview<P64>(ws_get(ctx, "force.Wo", hb), g, Ls);
   Half<P64> tmp = hview<P64>(ws_get(ctx, "force.tmp", hb), g, Ls);
-  op.mprec(cv(Xo), Y, tmp);                                            // Y = M X
-  op.hop(0, cv(Xo), Xe, false, true, -0.5, op.em(E_AINV));             // X_e = A^-1 B_eo X
-  op.fifth(cv(Y), Zo, E_AINVDAG);                                      // Y_o' = A^-dag Y
-  op.hop(0, cv(Zo), Ze, true, false, -0.5, op.em(E_AINVDAG_FDAG));     // Y_e' = A^-dag B_oe^dag Y_o'
-  op.fifth(cv(Xo), Wo, E_F);                                           // W_o = F X
-  op.fifth(cv(Xe), We, E_F);                                           // W_e = F X_e
-  DWF_CHECK_LAUNCH(launch_force(g->tables(), Ls, cv(We), cv(Wo), cv(Ze), cv(Zo),
-                                reinterpret_cast<const double2*>(Unat), p.tbc, p.dims, kind,
-                                reinterpret_cast<double2*>(Fout), s));
+  op.mprec(cv(Xo), Y, tmp);  // Y = M X
+  force_terms(ctx, op, Unat, cv(Xo), cv(Y), Fout, kind, 1.0, 0);
   return S;
 }
 
@@ -810,6 +822,91 @@ int fermion_force(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const voi
     info->wilson_apps = (long long)st.iters * Ls;
   }
   return 0;
+}
+
+// ------------------------------------------------------------------ Hasenbusch quotients
+// S_i = phi_i^dag M(m_i) (M(m_{i-1})^dag M(m_{i-1}))^-1 M(m_i)^dag phi_i  (Sec. 3 mass ladder),
+// i = 1..nq: the nq normal-equation solves run as one batched CG (every hop stage one launch
+// for all of them); then F = sum_i [e(-2 Re <Y_i, M(m_{i-1}) X_i>) - e(-2 Re <phi_i, M(m_i) X_i>)],
+// Y_i = M(m_{i-1}) X_i, accumulated into one force field.
+int quotient_force(dwf_ctx* ctx, const dwf_params& p, int nq, const double* masses, const void* Unat,
+                   const void* const* phi, void* F, double* S, int out_kind, void* const* x_io,
+                   dwf_solve_info* info) {
+  const auto t0 = Clock::now();
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const int Ls = p.Ls;
+  const size_t hb = half_size<P64>(g, Ls);
+  hipStream_t s = ctx->stream;
+  const double tol = info && info->tol > 0 ? info->tol : 1e-10;
+  const double delta = info && info->delta > 0 ? info->delta : 0.1;
+  const int maxit = info && info->maxit > 0 ? info->maxit : 100000;
+  void* U64 = ws_get(ctx, "quot.U64", 2 * g->nsites * 72 * sizeof(double2));
+  DWF_CHECK_LAUNCH(launch_pack_gauge<P64>(g->tables(), reinterpret_cast<const double2*>(Unat),
+                                          reinterpret_cast<double2*>(U64), s));
+  const void* Ui = links_in(ctx, g, U64, p.prec_inner, "quot");
+  Half<P64> to = hview<P64>(ws_get(ctx, "quot.to", hb), g, Ls);
+  Half<P64> te = hview<P64>(ws_get(ctx, "quot.te", hb), g, Ls);
+  std::vector<BatchSys> B(nq);
+  std::vector<void*> X(nq), chi(nq);
+  for (int i = 0; i < nq; ++i) {
+    dwf_params pn = p, pd = p;
+    pn.mass = masses[i + 1];
+    pd.mass = masses[i];
+    Op<P64> opn(ctx, g, pn, U64);
+    chi[i] = ws_get(ctx, "quot.chi." + std::to_string(i), hb);
+    X[i] = ws_get(ctx, "quot.X." + std::to_string(i), hb);
+    opn.mprec_dag(chview<P64>(phi[i], g, Ls), hview<P64>(chi[i], g, Ls), to, te);  // chi = M(m_i)^dag phi
+    if (x_io && x_io[i]) DWF_CHECK_HIP(hipMemcpyAsync(X[i], x_io[i], hb, hipMemcpyDeviceToDevice, s));
+    else DWF_CHECK_LAUNCH(launch_zero(X[i], hb, s));
+    BatchSys& b = B[i];
+    b.p = pd;
+    b.g = g;
+    b.U64 = U64;
+    b.Ui = Ui;
+    b.op64 = std::make_unique<Op<P64>>(ctx, g, pd, U64);
+    b.rhs = chview<P64>(chi[i], g, Ls);
+    b.x = hview<P64>(X[i], g, Ls);
+    b.tol_n = tol;
+  }
+  switch (p.prec_inner) {
+    case DWF_FP64: cg_batched<P64>(ctx, B, maxit, delta); break;
+    case DWF_FP32: cg_batched<P32>(ctx, B, maxit, delta); break;
+    case DWF_FP16: cg_batched<P16>(ctx, B, maxit, delta); break;
+    default: cg_batched<PB16>(ctx, B, maxit, delta); break;
+  }
+  double* part = partials_buf(ctx);
+  double* sc = scalars_buf(ctx);
+  Half<P64> Y = hview<P64>(ws_get(ctx, "quot.Y", hb), g, Ls);
+  long long iters = 0;
+  int status = 0;
+  for (int i = 0; i < nq; ++i) {
+    dwf_params pn = p, pd = p;
+    pn.mass = masses[i + 1];
+    pd.mass = masses[i];
+    Op<P64> opn(ctx, g, pn, U64), opd(ctx, g, pd, U64);
+    CHalf<P64> Xi = chview<P64>(X[i], g, Ls);
+    DWF_CHECK_LAUNCH(launch_dot<P64>(chview<P64>(chi[i], g, Ls), Xi, g->nsites * Ls, Ls, part, s));
+    DWF_CHECK_LAUNCH(launch_reduce(part, reduction_blocks(g->nsites * Ls), 2, sc, S_TMP1, 0, s));
+    if (S) S[i] = read_scalar(ctx, sc, S_TMP1);
+    opd.mprec(Xi, Y, te);  // Y = M(m_{i-1}) X
+    force_terms(ctx, opd, Unat, Xi, cv(Y), F, out_kind, 1.0, i > 0);
+    force_terms(ctx, opn, Unat, Xi, chview<P64>(phi[i], g, Ls), F, out_kind, -1.0, 1);
+    if (x_io && x_io[i]) DWF_CHECK_HIP(hipMemcpyAsync(x_io[i], X[i], hb, hipMemcpyDeviceToDevice, s));
+    iters += B[i].st.iters;
+    if (B[i].rr > B[i].target) status = DWF_NOT_CONVERGED;
+  }
+  DWF_CHECK_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = int(iters);
+    info->reliable_updates = 0;
+    for (auto& b : B) info->reliable_updates += b.st.reliable_updates;
+    double worst = 0.0;
+    for (auto& b : B) worst = std::max(worst, b.rhs2 > 0 ? std::sqrt(b.rr / b.rhs2) : 0.0);
+    info->true_rel_resid = worst;
+    info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    info->wilson_apps = iters * Ls;
+  }
+  return status;
 }
 
 }  // namespace dwf

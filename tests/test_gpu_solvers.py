@@ -183,3 +183,56 @@ def test_force_full_pipeline_and_fg_step(env, ora):
     assert info["iters"] - info["iters_first"] < info["iters_first"]
     # U unchanged
     assert rel_err(Ud.cpu().numpy(), U) == 0.0
+
+
+@pytest.mark.parametrize("prec,bc", [("fp64", (1.5, 0.5)), ("fp32", (1.0, 0.0))])
+def test_quotient_force_ladder_matches_oracle(env, ora, prec, bc):
+    """Hasenbusch mass ladder (Sec. 3): two quotient actions solved as one batched CG; the sum of
+    their forces and each action against the oracle's quotient force."""
+    import torch
+    dwf, ctx = env
+    dims, Ls = (4, 4, 4, 6), 8
+    masses = [0.02, 0.15, 1.0]
+    U = synth.random_links(dims, 0.5, 1501)
+    phis = [synth.gaussian_spinor_parity(dims, Ls, 1502 + i, 1) for i in range(2)]
+    Fo = 0.0
+    So = []
+    for i in range(2):
+        pn = ora.params(dims, Ls, mass=masses[i + 1], b=bc[0], c=bc[1], tbc=1)
+        pd = ora.params(dims, Ls, mass=masses[i], b=bc[0], c=bc[1], tbc=1)
+        S, F, _, _, _ = ora.quotient_force(pn, pd, U, phis[i], tol=1e-14)
+        Fo = Fo + F
+        So.append(S)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=masses[0], b=bc[0], c=bc[1], tbc=1)
+    Ud = lat.to_device(U)
+    phig = [lat.pack(ph, dwf.KIND_ODD) for ph in phis]
+    F = torch.zeros_like(Ud)
+    xs = [lat.zeros(dwf.KIND_ODD) for _ in range(2)]
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    info = dwf.quotient_force(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), masses, Ud, phig, F, x_io=xs,
+                              tol=tol)
+    print(prec, bc, info)
+    assert info["converged"]
+    err = rel_err(F.cpu().numpy(), Fo)
+    print("force rel err", err)
+    assert err < (1e-9 if prec == "fp64" else 1e-7)
+    for i in range(2):
+        assert abs(info["S"][i] - So[i]) < 1e-9 * abs(So[i])
+    # warm start from the returned solutions: (almost) no iterations
+    info2 = dwf.quotient_force(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), masses, Ud, phig, F, x_io=xs,
+                               tol=tol)
+    assert info2["iters"] <= 2 * 2
+    assert rel_err(F.cpu().numpy(), Fo) < (1e-9 if prec == "fp64" else 1e-7)
+
+
+def test_quotient_force_rejects_bad_ladders(env):
+    import torch
+    dwf, ctx = env
+    dims, Ls = (4, 4, 4, 4), 4
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.1)
+    Ud = lat.to_device(synth.random_links(dims, 0.5, 1510))
+    ph = lat.pack(synth.gaussian_spinor_parity(dims, Ls, 1511, 1), dwf.KIND_ODD)
+    F = torch.zeros_like(Ud)
+    for masses in ([0.2, 0.1], [0.1, 0.1], [0.1]):
+        with pytest.raises((dwf.DwfError, ValueError)):
+            dwf.quotient_force(ctx, lat.params(), masses, Ud, [ph], F)
