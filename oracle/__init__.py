@@ -81,6 +81,9 @@ def lib():
             "ora_madwf": ([P, P, vp, vp, vp, ci, cd, cd, cd, ci, ctypes.POINTER(MadwfInfo)], ci),
             "ora_action": ([P, vp, vp, vp, cd, ci, ctypes.POINTER(ci)], cd),
             "ora_force": ([P, vp, vp, vp, vp], None),
+            "ora_gauge_action": ([P, vp, cd], cd),
+            "ora_gauge_force": ([P, vp, cd, vp], None),
+            "ora_fgi_trajectory": ([P, cd, cd, ci, vp, vp, vp, cd, ci, ctypes.POINTER(cd), ctypes.POINTER(ci)], None),
             "ora_quotient_force": ([P, P, vp, vp, vp, vp, vp, cd, ci, ctypes.POINTER(ci)], cd),
             "ora_mat3_exp": ([vp, vp, ctypes.c_long], None),
             "ora_fg_force": ([P, vp, vp, cd, vp, vp, vp, cd, ci, vp], None),
@@ -298,6 +301,32 @@ def quotient_force(pn, pd, U, phi, x0=None, tol=1e-13, maxit=100000):
                                  e.ctypes.data_as(ctypes.c_void_p), float(tol), int(maxit), ctypes.byref(it))
     dims_r = tuple(int(pn.dims[k]) for k in (3, 2, 1, 0))
     return S, F.reshape((4,) + dims_r + (3, 3)), e.reshape((4,) + dims_r + (8,)), X, it.value
+
+
+def gauge_action(p, U, beta):
+    """Wilson plaquette action beta sum (1 - Re tr U_P / 3)."""
+    return lib().ora_gauge_action(ctypes.byref(p), _ptr(_c(U)), float(beta))
+
+
+def gauge_force(p, U, beta):
+    """F_mu(x) = sum_a e_a(S_g) T_a of the plaquette action, shaped like force()'s F."""
+    U = _c(U)
+    V = int(np.prod(p.dims))
+    F = np.zeros((4, V, 3, 3), np.complex128)
+    lib().ora_gauge_force(ctypes.byref(p), _ptr(U), float(beta), _ptr(F))
+    dims_r = tuple(int(p.dims[k]) for k in (3, 2, 1, 0))
+    return F.reshape((4,) + dims_r + (3, 3))
+
+
+def fgi_trajectory(p, beta, tau, n_steps, U, P, phi, tol=1e-13, maxit=100000):
+    """Force-gradient-integrator trajectory (Sec. 2) for S_g + phi^dag (M^dag M)^-1 phi.
+    Returns (U', P', (H_start, H_end), CG iterations); U, P are not modified."""
+    U1, P1, phi = _c(U).copy(), _c(P).copy(), _c(phi)
+    H = (ctypes.c_double * 2)()
+    it = ctypes.c_int(0)
+    lib().ora_fgi_trajectory(ctypes.byref(p), float(beta), float(tau), int(n_steps), _ptr(U1), _ptr(P1), _ptr(phi),
+                             float(tol), int(maxit), H, ctypes.byref(it))
+    return U1, P1, (H[0], H[1]), it.value
 
 
 def mat3_exp(A):

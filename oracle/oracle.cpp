@@ -916,4 +916,155 @@ void ora_fg_force(const ora_params* p, const cplx* U, const cplx* phi, double ta
   ora_force(p, Up.data(), X, Fp, nullptr);
 }
 
+
+// ---------------------------------------------------------------- gauge action, HMC (FGI)
+// Wilson plaquette action S_g = beta sum_{x, mu<nu} (1 - Re tr U_mu,nu(x) / 3) with
+// U_mu,nu(x) = U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag, periodic links (the
+// antiperiodic time boundary is a fermion boundary condition only).
+static void mat3_dag(const cplx* A, cplx* D) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) D[r * 3 + c] = std::conj(A[c * 3 + r]);
+}
+
+static long nb_periodic(const Geom& g, long i, int mu, int dir) {
+  int c[4];
+  coords_of(g, i, c);
+  c[mu] = (c[mu] + dir + g.L[mu]) % g.L[mu];
+  return index_of(g, c);
+}
+
+double ora_gauge_action(const ora_params* p, const cplx* U, double beta) {
+  Geom g = geom_of(p);
+  double sum = 0.0;
+#pragma omp parallel for reduction(+ : sum) schedule(static)
+  for (long i = 0; i < g.V; ++i)
+    for (int mu = 0; mu < 4; ++mu)
+      for (int nu = mu + 1; nu < 4; ++nu) {
+        cplx a[9], b[9], c[9], d[9], t1[9], t2[9];
+        mat3_mul(link(g, U, mu, i), link(g, U, nu, nb_periodic(g, i, mu, +1)), t1);
+        mat3_dag(link(g, U, mu, nb_periodic(g, i, nu, +1)), c);
+        mat3_dag(link(g, U, nu, i), d);
+        mat3_mul(t1, c, t2);
+        mat3_mul(t2, d, a);
+        (void)b;
+        sum += 1.0 - (a[0] + a[4] + a[8]).real() / 3.0;
+      }
+  return beta * sum;
+}
+
+// Force of the plaquette action: e_a(S_g) = -(beta/3) Re tr(T_a U_mu(x) A_mu(x)) with A the
+// sum of the six staples, so F_mu(x) = sum_a e_a T_a = (beta/6) TA(U_mu(x) A_mu(x)),
+// TA(M) = (M - M^dag)/2 - tr(M - M^dag)/6 (tr(T_a T_b) = -delta_ab / 2).
+void ora_gauge_force(const ora_params* p, const cplx* U, double beta, cplx* F) {
+  Geom g = geom_of(p);
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < g.V; ++i)
+    for (int mu = 0; mu < 4; ++mu) {
+      cplx A[9];
+      for (int k = 0; k < 9; ++k) A[k] = 0;
+      for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        cplx t1[9], t2[9], x1[9], x2[9];
+        // U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+        mat3_dag(link(g, U, mu, nb_periodic(g, i, nu, +1)), x1);
+        mat3_mul(link(g, U, nu, nb_periodic(g, i, mu, +1)), x1, t1);
+        mat3_dag(link(g, U, nu, i), x2);
+        mat3_mul(t1, x2, t2);
+        for (int k = 0; k < 9; ++k) A[k] += t2[k];
+        // U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
+        const long xm = nb_periodic(g, i, nu, -1);
+        mat3_dag(link(g, U, nu, nb_periodic(g, xm, mu, +1)), x1);
+        mat3_dag(link(g, U, mu, xm), x2);
+        mat3_mul(x1, x2, t1);
+        mat3_mul(t1, link(g, U, nu, xm), t2);
+        for (int k = 0; k < 9; ++k) A[k] += t2[k];
+      }
+      cplx M[9], Md[9];
+      mat3_mul(link(g, U, mu, i), A, M);
+      mat3_dag(M, Md);
+      cplx T[9];
+      for (int k = 0; k < 9; ++k) T[k] = 0.5 * (M[k] - Md[k]);
+      const cplx tr = (T[0] + T[4] + T[8]) / 3.0;
+      for (int d = 0; d < 3; ++d) T[d * 4] -= tr;
+      cplx* Fo = F + ((long)mu * g.V + i) * 9;
+      for (int k = 0; k < 9; ++k) Fo[k] = (beta / 6.0) * T[k];
+    }
+}
+
+// kinetic energy of momenta P = sum_a p_a T_a: sum p_a^2 / 2 = -sum tr(P P)
+static double kinetic(const Geom& g, const cplx* P) {
+  double k = 0.0;
+  for (long l = 0; l < 4 * g.V; ++l) {
+    const cplx* m = P + l * 9;
+    cplx t = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) t += m[r * 3 + c] * m[c * 3 + r];
+    k -= t.real();
+  }
+  return k;
+}
+
+// U <- exp(eps A) U on every link
+static void link_update(const Geom& g, const cplx* A, double eps, cplx* U) {
+#pragma omp parallel for schedule(static)
+  for (long l = 0; l < 4 * g.V; ++l) {
+    cplx a[9], e[9], u[9];
+    for (int k = 0; k < 9; ++k) a[k] = eps * A[l * 9 + k];
+    mat3_exp(a, e);
+    mat3_mul(e, U + l * 9, u);
+    for (int k = 0; k < 9; ++k) U[l * 9 + k] = u[k];
+  }
+}
+
+// force of S = S_g + phi^dag (M^dag M)^-1 phi at U; X: initial guess in, solution out.
+// Returns S_f; F = F_g + F_f.
+static double total_force(const ora_params* p, double beta, const cplx* U, const cplx* phi, cplx* X, cplx* F,
+                          double tol, int maxit, int* iters) {
+  Geom g = geom_of(p);
+  const long nl = 4 * g.V;
+  std::vector<cplx> Fg(nl * 9);
+  int it = 0;
+  const double Sf = ora_action(p, U, phi, X, tol, maxit, &it);
+  *iters += it;
+  ora_force(p, U, X, F, nullptr);
+  ora_gauge_force(p, U, beta, Fg.data());
+  for (long k = 0; k < nl * 9; ++k) F[k] += Fg[k];
+  return Sf;
+}
+
+// One molecular-dynamics trajectory of the force-gradient integrator (Sec. 2), n_steps steps
+// of size tau of
+//   exp(tau/6 z_S) exp(tau/2 z_T) exp(2 tau/3 z_S - tau^3/72 z_{S,{S,T}}) exp(tau/2 z_T) exp(tau/6 z_S)
+// for H = sum p_a^2 / 2 + S_g + phi^dag (M^dag M)^-1 phi, with z_T: U <- exp(eps P) U and
+// z_S: P <- P - eps F.  The middle momentum update takes the force at
+// U' = exp(-tau^2/24 F(U)) U (the two-step form of the force-gradient term), its solve
+// started from X(U); every other solve starts from zero.  The force at the end of a step is
+// the force at the start of the next.  U, P (natural layouts) are updated in place;
+// H[0], H[1] get H at the start and at the end; *iters the CG iteration total.
+void ora_fgi_trajectory(const ora_params* p, double beta, double tau, int n_steps, cplx* U, cplx* P,
+                        const cplx* phi, double tol, int maxit, double* H, int* iters) {
+  Geom g = geom_of(p);
+  const long nl = 4 * g.V, n = g.V * 12 * p->Ls;
+  std::vector<cplx> F(nl * 9), F1(nl * 9), Up(nl * 9), X(n), X1(n);
+  *iters = 0;
+  std::fill(X.begin(), X.end(), cplx(0));
+  double Sf = total_force(p, beta, U, phi, X.data(), F.data(), tol, maxit, iters);
+  H[0] = kinetic(g, P) + ora_gauge_action(p, U, beta) + Sf;
+  for (int step = 0; step < n_steps; ++step) {
+    for (long k = 0; k < nl * 9; ++k) P[k] -= (tau / 6.0) * F[k];
+    link_update(g, P, tau / 2.0, U);
+    std::fill(X1.begin(), X1.end(), cplx(0));
+    total_force(p, beta, U, phi, X1.data(), F1.data(), tol, maxit, iters);
+    std::copy(U, U + nl * 9, Up.begin());
+    link_update(g, F1.data(), -tau * tau / 24.0, Up.data());
+    total_force(p, beta, Up.data(), phi, X1.data(), F1.data(), tol, maxit, iters);
+    for (long k = 0; k < nl * 9; ++k) P[k] -= (2.0 * tau / 3.0) * F1[k];
+    link_update(g, P, tau / 2.0, U);
+    std::fill(X.begin(), X.end(), cplx(0));
+    Sf = total_force(p, beta, U, phi, X.data(), F.data(), tol, maxit, iters);
+    for (long k = 0; k < nl * 9; ++k) P[k] -= (tau / 6.0) * F[k];
+  }
+  H[1] = kinetic(g, P) + ora_gauge_action(p, U, beta) + Sf;
+}
+
 }  // extern "C"

@@ -477,3 +477,73 @@ def test_quotient_of_equal_masses_is_constant(ora):
     _, X1, _ = ora.action(p, U, phi, tol=1e-14)
     F1, _ = ora.force(p, U, X1)
     assert np.max(np.abs(F)) < 1e-9 * np.max(np.abs(F1))
+
+
+def _momenta(ora, dims, seed):
+    T = ora.generators()
+    V = int(np.prod(dims))
+    c = synth.random_su3_algebra(4 * V, seed)
+    return np.einsum("na,aij->nij", c, T).reshape((4,) + tuple(dims[::-1]) + (3, 3)), c
+
+
+def test_gauge_action_and_force(ora):
+    """Plaquette action: zero on unit links, gauge invariant; its force against fourth-order
+    central differences of the action along exp(+-h T_a)."""
+    dims = (2, 4, 2, 4)
+    p = ora.params(dims, 2)
+    beta = 2.3
+    assert abs(ora.gauge_action(p, synth.unit_links(dims), beta)) < 1e-12
+    U = synth.random_links(dims, 0.5, 151)
+    S0 = ora.gauge_action(p, U, beta)
+    G = synth.random_gauge_transform(dims, 152)
+    assert abs(ora.gauge_action(p, gauge_transform(U, G), beta) - S0) < 1e-11 * abs(S0)
+    F = ora.gauge_force(p, U, beta)
+    T = ora.generators()
+    h = 1e-3
+    for (mu, t, z, y, x, a) in synth.sample_links(dims, 12, 153):
+        Sv = {k: ora.gauge_action(p, perturb_link(U, mu, t, z, y, x, scipy.linalg.expm(k * h * T[a])), beta)
+              for k in (-2, -1, 1, 2)}
+        fd = (8 * (Sv[1] - Sv[-1]) - (Sv[2] - Sv[-2])) / (12 * h)
+        e_a = -2.0 * np.trace(T[a] @ F[mu, t, z, y, x]).real  # F = sum_a e_a T_a, tr(T_a T_b) = -delta/2
+        assert abs(fd - e_a) <= 1e-8 * max(abs(fd), 1.0)
+
+
+def test_fgi_trajectory_is_reversible(ora):
+    """Sec. 2: the force-gradient integrator is symmetric -- integrating back from (U', -P')
+    returns to (U, -P) up to the solver tolerance."""
+    dims, Ls = (2, 2, 2, 4), 4
+    p = ora.params(dims, Ls, M5=1.8, mass=0.1)
+    U = synth.random_links(dims, 0.3, 161)
+    phi = ora.mprec(p, U, synth.gaussian_spinor_parity(dims, Ls, 162, 1), dagger=True)
+    P, _ = _momenta(ora, dims, 163)
+    U1, P1, H, _ = ora.fgi_trajectory(p, 2.0, 0.125, 4, U, P, phi)
+    U2, P2, H2, _ = ora.fgi_trajectory(p, 2.0, 0.125, 4, U1, -P1, phi)
+    assert np.max(np.abs(U2 - U)) < 1e-11
+    assert np.max(np.abs(P2 + P)) < 1e-10
+    assert abs(H2[1] - H[0]) < 1e-9
+    assert abs(H2[0] - H[1]) < 1e-9
+
+
+def test_fgi_energy_violation_scales_as_tau4(ora):
+    """The integrator is fourth order with the two-step force-gradient term (Sec. 2): at fixed
+    trajectory length dH ~ tau^4.  Gauge action alone (exact asymptotics at these step sizes),
+    and with the fermion action (rougher: smaller steps).  A sign error in the force-gradient
+    term leaves a second-order integrator (ratio 4 per halving)."""
+    dims, Ls = (2, 2, 2, 4), 4
+    p = ora.params(dims, Ls, M5=1.8, mass=0.1)
+    U = synth.random_links(dims, 0.3, 171)
+    eta = synth.gaussian_spinor_parity(dims, Ls, 172, 1)
+    phi = ora.mprec(p, U, eta, dagger=True)
+    P, c = _momenta(ora, dims, 173)
+    # kinetic energy of P = sum p_a T_a is sum p_a^2 / 2
+    _, _, H, _ = ora.fgi_trajectory(p, 2.0, 0.1, 1, U, P, 0 * phi)
+    assert abs((H[0] - ora.gauge_action(p, U, 2.0)) - 0.5 * np.sum(c ** 2)) < 1e-9
+    dH = {}
+    for n in (8, 16):
+        _, _, H, _ = ora.fgi_trajectory(p, 2.0, 0.5 / n, n, U, P, 0 * phi)
+        dH[n] = H[1] - H[0]
+    assert abs(dH[8] / dH[16] - 16.0) < 0.5
+    for n in (16, 32):
+        _, _, H, _ = ora.fgi_trajectory(p, 2.0, 0.5 / n, n, U, P, phi)
+        dH[n] = H[1] - H[0]
+    assert 12.0 < dH[16] / dH[32] < 20.0
