@@ -173,6 +173,32 @@ def hasenbusch_ladder(dwf, ctx, prec="fp32", tol=1e-6):
             "iters": info["iters"], "iters_sequential": iters_seq, "S": info["S"]}
 
 
+def fgi_measure(dwf, ctx, prec="fp32", tol=1e-8, n_steps=2, tau=0.1, beta=5.7, eps=0.5, mass=0.01):
+    """Force-gradient-integrator trajectory (Sec. 2) on the 16^3 x 32, Ls = 16 force lattice
+    (m = 0.01): wall time per step, energy violation, and the iterations the force-gradient
+    forecasting saves (solves at U' started from X(U) vs those at U)."""
+    import torch
+    import synth
+    dims, Ls = (16, 16, 16, 32), 16
+    lat = dwf.Lattice(ctx, dims, Ls, mass=mass)
+    U = synth.random_links(dims, eps, synth.link_seed(4))
+    Ud = lat.to_device(U)
+    U64 = lat.pack_gauge(U)
+    eta = lat.pack(synth.gaussian_spinor_parity(dims, Ls, synth.source_seed(4, 5), 1), dwf.KIND_ODD)
+    phi = lat.empty(dwf.KIND_ODD)
+    dwf.dwf_dslash(ctx, lat.params(), U64, eta, phi, dwf.OP_MPREC, 1, True)  # phi = M^dag eta
+    P = lat.to_device(synth.random_momenta(dims, synth.source_seed(4, 6)))
+    torch.cuda.synchronize()
+    info = dwf.hmc_fgi_trajectory(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), Ud, P, phi, beta, tau, n_steps,
+                                  tol=tol)
+    return {"workload": f"FGI trajectory, Shamir DWF 16^3x32 Ls=16 M5=1.8 m={mass} + Wilson plaquette beta={beta}, "
+                        f"random SU(3) links eps={eps}, Gaussian momenta, phi = M^dag eta, {n_steps} steps of "
+                        f"tau={tau}, {prec} force solves to {tol:g}",
+            "seconds": info["seconds"], "seconds_per_step": info["seconds"] / n_steps,
+            "force_evals": info["force_evals"], "dH": info["H_end"] - info["H_start"], "cg_iters": info["cg_iters"],
+            "fg_iters_first": info["fg_iters_first"], "fg_iters_forecast": info["fg_iters_forecast"]}
+
+
 def cpu_baseline(workload, U, b_nat, fp64_iters, seconds_budget=25.0):
     """FP64 oracle on the host cores: time M_prec^dag M_prec on the same operator,
     restricted to a bounded sample (one or more applications on the workload's lattice
@@ -319,6 +345,17 @@ def main():
         log(f"Hasenbusch ladder force: batched {ladder['batched_s']:.3f} s, one at a time "
             f"{ladder['sequential_s']:.3f} s")
 
+    fgi = None
+    if not args.no_extras:
+        # a fixed trajectory length 0.08 at two step sizes: dH of a fourth-order integrator
+        # drops 16x when the step halves
+        kw = dict(prec="fp64", tol=1e-12, beta=5.7, eps=0.2, mass=0.5)
+        runs = [fgi_measure(dwf, ctx, n_steps=n, tau=0.08 / n, **kw) for n in (2, 4)]
+        fgi = dict(runs[1], dH_tau_2x=runs[0]["dH"], dH_ratio=runs[0]["dH"] / runs[1]["dH"])
+        log(f"FGI trajectory: {fgi['seconds_per_step']:.2f} s per step, dH {runs[0]['dH']:.3e} -> {fgi['dH']:.3e} "
+            f"(ratio {fgi['dH_ratio']:.1f}), forecast solves {fgi['fg_iters_forecast']} vs "
+            f"{fgi['fg_iters_first']} iterations")
+
     cpu = None
     if not args.no_cpu_baseline and fp64 is not None:
         log("CPU oracle baseline ...")
@@ -365,6 +402,7 @@ def main():
                             for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["ms"])},
         "cpu_baseline": cpu,
         "hasenbusch_ladder": ladder,
+        "fgi_trajectory": fgi,
         "paper_context": "Table 1 (BG/P, 512 nodes, 32^3x64, L=32 -> L'=12): 1.8x fewer 4D Wilson "
                          "applications, 42% of the direct-CG wall time",
     }

@@ -190,6 +190,32 @@ int mobius_accel_solve(dwf_ctx* ctx, const dwf_params* target, const dwf_params*
 int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U_natural, const void* phi, void* F, double* S,
                   double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
 
+/* One molecular-dynamics trajectory of the force-gradient integrator (Sec. 2):
+ * per step of size tau the PQPQP sequence
+ *   P -= tau/6 F(U); U = exp(tau/2 P) U;
+ *   P -= 2 tau/3 F(U') with U' = exp(-tau^2/24 F(U)) U (its solve started from X(U));
+ *   U = exp(tau/2 P) U; P -= tau/6 F(U),
+ * for H = sum_a p_a^2 / 2 + S_g + phi^+ (M_prec^+ M_prec)^-1 phi, S_g = the Wilson
+ * plaquette action with coupling beta (periodic links), F = sum_a e_a(S) T_a.
+ * U (natural link layout) and P (momenta P = sum_a p_a T_a, same layout, traceless
+ * anti-Hermitian), both device complex128, are updated in place; phi: packed FP64
+ * odd half (held fixed).  The force solves run in p->prec_inner to the normal-
+ * equation tolerance info->tol.  Fills H_start, H_end and the counters. */
+typedef struct {
+  double beta;             /* plaquette coupling */
+  double tau;              /* step size */
+  int n_steps;
+  double tol, delta;       /* force solves: normal-equation tolerance, reliable-update delta */
+  int maxit;
+  double H_start, H_end;   /* out */
+  int force_evals;         /* out: force evaluations (3 per step + 1) */
+  long long cg_iters;      /* out: all CG iterations */
+  long long fg_iters_first, fg_iters_forecast; /* out: iterations of the solves at U and at U' */
+  double seconds;          /* out */
+} dwf_hmc_info;
+int hmc_fgi_trajectory(dwf_ctx* ctx, const dwf_params* p, void* U_natural, void* P_natural, const void* phi,
+                       dwf_hmc_info* info);
+
 /* Hasenbusch mass ladder (Sec. 3): the quotient actions
  *   S_i = phi_i^+ M(m_i) (M(m_{i-1})^+ M(m_{i-1}))^-1 M(m_i)^+ phi_i,   i = 1..nq,
  * M = M_prec of p with its mass replaced by masses[] (nq + 1 entries,

@@ -61,6 +61,17 @@ class MadwfInfo(ctypes.Structure):
         return d
 
 
+class HmcInfo(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("tau", ctypes.c_double), ("n_steps", ctypes.c_int),
+                ("tol", ctypes.c_double), ("delta", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("H_start", ctypes.c_double), ("H_end", ctypes.c_double), ("force_evals", ctypes.c_int),
+                ("cg_iters", ctypes.c_longlong), ("fg_iters_first", ctypes.c_longlong),
+                ("fg_iters_forecast", ctypes.c_longlong), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 # exported symbols of include/dwf.h with their ctypes signatures
@@ -86,6 +97,7 @@ SIGNATURES = {
     "dwf_tune_get": ([_vp, _ci, _ci, _ci] + [ctypes.POINTER(_ci)] * 4, _ci),
     "quotient_force": ([_vp, _PP, _ci, ctypes.POINTER(_cd), _vp, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_cd), _ci,
                         ctypes.POINTER(_vp), ctypes.POINTER(SolveInfo)], _ci),
+    "hmc_fgi_trajectory": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(HmcInfo)], _ci),
     "dwf_timing_enable": ([_vp, _ci], _ci),
     "dwf_timing_report": ([_vp, ctypes.c_char_p, ctypes.c_size_t], _ci),
 }
@@ -257,6 +269,16 @@ def quotient_force(ctx, p, masses, U_natural, phis, F, out_kind=0, x_io=None, to
     d["S"] = [S[i] for i in range(nq)]
     d["converged"] = rc == DWF_OK
     return d
+
+
+def hmc_fgi_trajectory(ctx, p, U_natural, P_natural, phi, beta, tau, n_steps, tol=1e-10, delta=0.1, maxit=100000):
+    """One force-gradient-integrator trajectory (Sec. 2); U and P are updated in place."""
+    info = HmcInfo()
+    info.beta, info.tau, info.n_steps = float(beta), float(tau), int(n_steps)
+    info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
+    _check(lib().hmc_fgi_trajectory(ctx.handle, ctypes.byref(p), _vp(_ptr(U_natural)), _vp(_ptr(P_natural)),
+                                    _vp(_ptr(phi)), ctypes.byref(info)))
+    return info.as_dict()
 
 
 def dwf_tune_set(ctx, prec, Ls, sites_per_block, s_per_thread, xcd_remap=1, link_lds=1, kernel_id=0):

@@ -384,6 +384,16 @@ int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* 
   return guarded([&]() { return dwf::fermion_force(ctx, *p, U, phi, F, S, tau_fg, out_kind, x_io, info); });
 }
 
+int hmc_fgi_trajectory(dwf_ctx* ctx, const dwf_params* p, void* U, void* P, const void* phi, dwf_hmc_info* info) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  int rc = check_params(p, true);
+  if (rc) return rc;
+  if (!U || !P || !phi || !info) return fail(DWF_ERR_ARG, "NULL pointer");
+  if (info->n_steps < 0 || !(info->tau > 0.0) || !std::isfinite(info->tau) || !std::isfinite(info->beta))
+    return fail(DWF_ERR_ARG, "need tau > 0, n_steps >= 0, finite beta");
+  return guarded([&]() { return dwf::fgi_trajectory(ctx, *p, U, P, phi, info); });
+}
+
 int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* masses, const void* U,
                    const void* const* phi, void* F, double* S, int out_kind, void* const* x_io,
                    dwf_solve_info* info) {

@@ -137,6 +137,14 @@ int launch_convert_links(const typename Pi::S* in, typename Po::S* out, long n, 
 int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CHalf<P64> Z_e, CHalf<P64> Z_o,
                  const double2* U_natural, int tbc, const int dims[4], int kind, double2* F, hipStream_t st,
                  double coef = 1.0, int accumulate = 0);
+// gauge-field kernels (natural layouts, periodic links): plaquette action partial sums
+// (sum (1 - Re tr U_P / 3) per workgroup), the plaquette force F = coef (beta/6) TA(U A)
+// (+ F with accumulate), P <- P - eps F, kinetic-energy partial sums (-tr P P per link)
+int launch_plaquette(const double2* U, const int dims[4], double* partials, int* nblocks, hipStream_t st);
+int launch_gauge_force(const double2* U, const int dims[4], double beta, double coef, int accumulate, double2* F,
+                       hipStream_t st);
+int launch_mom_update(double2* P, const double2* F, double eps, long nlinks, hipStream_t st);
+int launch_kinetic(const double2* P, long nlinks, double* partials, int* nblocks, hipStream_t st);
 // U' = exp(-eps F) U per link (Cayley-Hamilton exponential), natural layouts
 int launch_fg_update(const double2* F, const double2* U, double eps, double2* Uout, long nlinks, hipStream_t st);
 

@@ -909,4 +909,89 @@ int quotient_force(dwf_ctx* ctx, const dwf_params& p, int nq, const double* mass
   return status;
 }
 
+
+// ------------------------------------------------------------------ force-gradient integrator
+// One molecular-dynamics trajectory (Sec. 2) of
+//   exp(tau/6 z_S) exp(tau/2 z_T) exp(2 tau/3 z_S - tau^3/72 z_{S,{S,T}}) exp(tau/2 z_T) exp(tau/6 z_S)
+// per step for H = sum p_a^2 / 2 + S_g + phi^+ (M^+ M)^-1 phi, z_T: U <- exp(eps P) U,
+// z_S: P <- P - eps F.  The middle momentum update uses the force at
+// U' = exp(-tau^2/24 F(U)) U with its solve started from X(U) (force-gradient forecasting);
+// the other solves start from zero; the force at the end of a step opens the next one.
+static double total_force(dwf_ctx* ctx, const dwf_params& p, double beta, const void* U, const void* phi, void* X,
+                          void* F, double tol_n, int maxit, double delta, SolveStats* st) {
+  const double Sf = force_at(ctx, p, U, phi, X, F, 0, tol_n, maxit, delta, st);
+  DWF_CHECK_LAUNCH(launch_gauge_force(reinterpret_cast<const double2*>(U), p.dims, beta, 1.0, 1,
+                                      reinterpret_cast<double2*>(F), ctx->stream));
+  return Sf;
+}
+
+static double partial_sum(dwf_ctx* ctx, int nblocks) {
+  double* sc = scalars_buf(ctx);
+  DWF_CHECK_LAUNCH(launch_reduce(partials_buf(ctx), nblocks, 1, sc, S_TMP2, 0, ctx->stream));
+  return read_scalar(ctx, sc, S_TMP2);
+}
+
+static double hamiltonian(dwf_ctx* ctx, const dwf_params& p, double beta, const void* U, const void* P, double Sf,
+                          long nlinks) {
+  int nb = 0;
+  DWF_CHECK_LAUNCH(launch_kinetic(reinterpret_cast<const double2*>(P), nlinks, partials_buf(ctx), &nb, ctx->stream));
+  const double K = partial_sum(ctx, nb);
+  DWF_CHECK_LAUNCH(launch_plaquette(reinterpret_cast<const double2*>(U), p.dims, partials_buf(ctx), &nb, ctx->stream));
+  const double Sg = beta * partial_sum(ctx, nb);
+  return K + Sg + Sf;
+}
+
+int fgi_trajectory(dwf_ctx* ctx, const dwf_params& p, void* U, void* P, const void* phi, dwf_hmc_info* info) {
+  const auto t0 = Clock::now();
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const size_t hb = half_size<P64>(g, p.Ls);
+  const long nl = 4 * g->V;
+  hipStream_t s = ctx->stream;
+  const double beta = info->beta, tau = info->tau;
+  const double tol = info->tol > 0 ? info->tol : 1e-10;
+  const double delta = info->delta > 0 ? info->delta : 0.1;
+  const int maxit = info->maxit > 0 ? info->maxit : 100000;
+  void* F = ws_get(ctx, "hmc.F", nl * 9 * sizeof(double2));
+  void* F1 = ws_get(ctx, "hmc.F1", nl * 9 * sizeof(double2));
+  void* Up = ws_get(ctx, "hmc.Uprime", nl * 9 * sizeof(double2));
+  void* X = ws_get(ctx, "hmc.X", hb);
+  void* X1 = ws_get(ctx, "hmc.X1", hb);
+  double2* Pd = reinterpret_cast<double2*>(P);
+  double2* Ud = reinterpret_cast<double2*>(U);
+  SolveStats st;
+  int evals = 0, fg_first = 0, fg_second = 0;
+  DWF_CHECK_LAUNCH(launch_zero(X, hb, s));
+  double Sf = total_force(ctx, p, beta, U, phi, X, F, tol, maxit, delta, &st);
+  ++evals;
+  info->H_start = hamiltonian(ctx, p, beta, U, P, Sf, nl);
+  for (int step = 0; step < info->n_steps; ++step) {
+    DWF_CHECK_LAUNCH(launch_mom_update(Pd, reinterpret_cast<const double2*>(F), tau / 6.0, nl, s));
+    DWF_CHECK_LAUNCH(launch_fg_update(Pd, Ud, -tau / 2.0, Ud, nl, s));  // U <- exp(tau/2 P) U
+    DWF_CHECK_LAUNCH(launch_zero(X1, hb, s));
+    int before = st.iters;
+    total_force(ctx, p, beta, U, phi, X1, F1, tol, maxit, delta, &st);
+    fg_first += st.iters - before;
+    // force-gradient step: U' = exp(-tau^2/24 F1) U, force at U' from X(U)
+    DWF_CHECK_LAUNCH(launch_fg_update(reinterpret_cast<const double2*>(F1), Ud, tau * tau / 24.0,
+                                      reinterpret_cast<double2*>(Up), nl, s));
+    before = st.iters;
+    total_force(ctx, p, beta, Up, phi, X1, F1, tol, maxit, delta, &st);
+    fg_second += st.iters - before;
+    DWF_CHECK_LAUNCH(launch_mom_update(Pd, reinterpret_cast<const double2*>(F1), 2.0 * tau / 3.0, nl, s));
+    DWF_CHECK_LAUNCH(launch_fg_update(Pd, Ud, -tau / 2.0, Ud, nl, s));
+    DWF_CHECK_LAUNCH(launch_zero(X, hb, s));
+    Sf = total_force(ctx, p, beta, U, phi, X, F, tol, maxit, delta, &st);
+    DWF_CHECK_LAUNCH(launch_mom_update(Pd, reinterpret_cast<const double2*>(F), tau / 6.0, nl, s));
+    evals += 3;
+  }
+  info->H_end = hamiltonian(ctx, p, beta, U, P, Sf, nl);
+  DWF_CHECK_HIP(hipStreamSynchronize(s));
+  info->force_evals = evals;
+  info->cg_iters = st.iters;
+  info->fg_iters_first = fg_first;
+  info->fg_iters_forecast = fg_second;
+  info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+  return 0;
+}
+
 }  // namespace dwf

@@ -22,6 +22,7 @@ int madwf(dwf_ctx* ctx, const dwf_params& pt, const dwf_params& pi, const void* 
           dwf_madwf_info* info);
 int fermion_force(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const void* phi, void* F, double* S,
                   double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
+int fgi_trajectory(dwf_ctx* ctx, const dwf_params& p, void* U, void* P, const void* phi, dwf_hmc_info* info);
 int quotient_force(dwf_ctx* ctx, const dwf_params& p, int nq, const double* masses, const void* Unat,
                    const void* const* phi, void* F, double* S, int out_kind, void* const* x_io,
                    dwf_solve_info* info);

@@ -89,6 +89,26 @@ def random_su3_algebra(n, seed):
     return _rng(seed).standard_normal((n, 8))
 
 
+def random_momenta(dims, seed):
+    """Gaussian momenta P = i H on every link, H Hermitian traceless distributed as
+    sum_a p_a lambda_a / 2 with independent p_a ~ N(0, 1) (Gell-Mann matrices lambda_a): the
+    off-diagonal entries (x + i y) / 2, x, y ~ N(0, 1); the diagonal (p3 / 2 + p8 / (2 sqrt 3),
+    -p3 / 2 + p8 / (2 sqrt 3), -p8 / sqrt 3).  Shape [4][T][Z][Y][X][3][3]."""
+    X, Y, Z, T = dims
+    rng = _rng(seed)
+    n = 4 * X * Y * Z * T
+    H = np.zeros((n, 3, 3), np.complex128)
+    for (i, j) in ((0, 1), (0, 2), (1, 2)):
+        v = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) / 2
+        H[:, i, j] = v
+        H[:, j, i] = np.conj(v)
+    p3, p8 = rng.standard_normal(n), rng.standard_normal(n)
+    H[:, 0, 0] = p3 / 2 + p8 / (2 * np.sqrt(3))
+    H[:, 1, 1] = -p3 / 2 + p8 / (2 * np.sqrt(3))
+    H[:, 2, 2] = -p8 / np.sqrt(3)
+    return (1j * H).reshape((4, T, Z, Y, X, 3, 3))
+
+
 def sample_links(dims, count, seed):
     """Seeded choice of (mu, t, z, y, x, a) link/generator coordinates."""
     X, Y, Z, T = dims

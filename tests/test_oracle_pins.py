@@ -547,3 +547,17 @@ def test_fgi_energy_violation_scales_as_tau4(ora):
         _, _, H, _ = ora.fgi_trajectory(p, 2.0, 0.5 / n, n, U, P, phi)
         dH[n] = H[1] - H[0]
     assert 12.0 < dH[16] / dH[32] < 20.0
+
+
+def test_random_momenta_distribution(ora):
+    """synth.random_momenta draws P = sum_a p_a T_a with p_a ~ N(0, 1): traceless
+    anti-Hermitian, and its generator coefficients p_a = -2 tr(T_a P) have unit variance and
+    no correlation."""
+    dims = (8, 8, 8, 8)  # 16384 links: sampling error of the covariance about 0.01
+    P = synth.random_momenta(dims, 181).reshape(-1, 3, 3)
+    assert np.max(np.abs(P + np.conj(np.swapaxes(P, -1, -2)))) < 1e-15
+    assert np.max(np.abs(np.trace(P, axis1=-2, axis2=-1))) < 1e-15
+    T = ora.generators()
+    c = -2 * np.einsum("aij,nji->na", T, P).real
+    cov = np.cov(c.T)
+    assert np.max(np.abs(cov - np.eye(8))) < 0.06
