@@ -34,7 +34,8 @@ def build(force=False):
 class Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("Ls", ctypes.c_int), ("tbc", ctypes.c_int),
                 ("M5", ctypes.c_double), ("mass", ctypes.c_double),
-                ("b", ctypes.c_double), ("c", ctypes.c_double)]
+                ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("bs", ctypes.c_void_p), ("cs", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -96,13 +97,23 @@ def lib():
     return _lib
 
 
-def params(dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0):
-    """Operator parameters: extents (X,Y,Z,T), Ls, M5, m, Moebius b and c (Shamir: 1, 0)."""
+def params(dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0, bs=None, cs=None):
+    """Operator parameters: extents (X,Y,Z,T), Ls, M5, m, Moebius b and c (Shamir: 1, 0);
+    bs, cs (optional, Ls entries each): s-dependent Moebius coefficients b_s, c_s."""
     p = Params()
     for k in range(4):
         p.dims[k] = int(dims[k])
     p.Ls, p.tbc = int(Ls), int(tbc)
     p.M5, p.mass, p.b, p.c = float(M5), float(mass), float(b), float(c)
+    keep = []
+    for name, arr in (("bs", bs), ("cs", cs)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64)
+            if a.shape != (int(Ls),):
+                raise ValueError(f"{name} must hold Ls entries")
+            keep.append(a)
+            setattr(p, name, a.ctypes.data)
+    p._keep = keep  # the arrays live as long as the parameter block
     return p
 
 

@@ -47,7 +47,13 @@ typedef struct {
   int Ls;
   int tbc;
   double M5, mass, b, c;
+  const double* bs;  // optional s-dependent Moebius coefficients b_s, c_s (Ls entries each;
+  const double* cs;  // NULL: the constants b, c)
 } ora_params;
+
+// Moebius coefficients of slice s (Sec. 4 admits any Moebius operator: s-dependent b_s, c_s)
+static inline double bco(const ora_params* p, int s) { return p->bs ? p->bs[s] : p->b; }
+static inline double cco(const ora_params* p, int s) { return p->cs ? p->cs[s] : p->c; }
 
 typedef struct {
   int iters;             // CG iterations (normal-equation operator applications)
@@ -242,6 +248,7 @@ void stilde(const Geom& g, int Ls, double m, const cplx* in, cplx* out, int dagg
 // 5D operator D(m) (Moebius; Shamir at b=1,c=0) and its explicitly written adjoint
 //   D   = (b D_W + 1) + (c D_W - 1) S~
 //   D^+ = (b D_W^+ + 1) + S~^+ (c D_W^+ - 1)
+// (b = diag(b_s), c = diag(c_s) with s-dependent coefficients)
 void dwf5(const ora_params* p, const cplx* U, const cplx* in, cplx* out, int dagger) {
   Geom g = geom_of(p);
   const int Ls = p->Ls;
@@ -254,15 +261,18 @@ void dwf5(const ora_params* p, const cplx* U, const cplx* in, cplx* out, int dag
       dw4(g, p->M5, U, t.data() + s * V12, w.data() + s * V12, 0); // D_W (S~psi)_s
     }
 #pragma omp parallel for schedule(static)
-    for (long k = 0; k < n; ++k) out[k] = p->b * out[k] + in[k] + p->c * w[k] - t[k];
+    for (long k = 0; k < n; ++k) {
+      const int s = int(k / V12);
+      out[k] = bco(p, s) * out[k] + in[k] + cco(p, s) * w[k] - t[k];
+    }
   } else {
     for (int s = 0; s < Ls; ++s) dw4(g, p->M5, U, in + s * V12, w.data() + s * V12, 1);
     // t = c D_W^+ psi - psi
 #pragma omp parallel for schedule(static)
-    for (long k = 0; k < n; ++k) t[k] = p->c * w[k] - in[k];
+    for (long k = 0; k < n; ++k) t[k] = cco(p, int(k / V12)) * w[k] - in[k];
     stilde(g, Ls, p->mass, t.data(), out, 1);
 #pragma omp parallel for schedule(static)
-    for (long k = 0; k < n; ++k) out[k] += p->b * w[k] + in[k];
+    for (long k = 0; k < n; ++k) out[k] += bco(p, int(k / V12)) * w[k] + in[k];
   }
 }
 
@@ -282,15 +292,15 @@ FifthMatrix build_A(const ora_params* p) {
   A.n = n;
   A.a.assign((size_t)n * n, 0.0);
   for (int s = 0; s < Ls; ++s) {
-    for (int al = 0; al < 4; ++al) A.a[(s * 4 + al) * n + s * 4 + al] += p->b * d + 1.0;
+    for (int al = 0; al < 4; ++al) A.a[(s * 4 + al) * n + s * 4 + al] += bco(p, s) * d + 1.0;
     int sp = s + 1, sm = s - 1;
     double fp = 1.0, fm = 1.0;
     if (sp == Ls) { sp = 0; fp = -p->mass; }
     if (sm < 0) { sm = Ls - 1; fm = -p->mass; }
     for (int al = 0; al < 4; ++al)
       for (int be = 0; be < 4; ++be) {
-        A.a[(s * 4 + al) * n + sp * 4 + be] += (p->c * d - 1.0) * fp * G.pminus[al][be];
-        A.a[(s * 4 + al) * n + sm * 4 + be] += (p->c * d - 1.0) * fm * G.pplus[al][be];
+        A.a[(s * 4 + al) * n + sp * 4 + be] += (cco(p, s) * d - 1.0) * fp * G.pminus[al][be];
+        A.a[(s * 4 + al) * n + sm * 4 + be] += (cco(p, s) * d - 1.0) * fm * G.pplus[al][be];
       }
   }
   return A;
@@ -364,12 +374,21 @@ void mask_parity(const Geom& g, int Ls, cplx* f, int keep) {
         for (int k = 0; k < 12; ++k) f[s * V12 + i * 12 + k] = 0;
 }
 
-// F = b + c S~ (and F^dag = b + c S~^dag), site-local
+// F = b + c S~ (and F^dag = b + S~^dag c), site-local, b = diag(b_s), c = diag(c_s)
 void apply_F(const ora_params* p, const Geom& g, const cplx* in, cplx* out, int dagger) {
-  const long n = g.V * 12 * p->Ls;
-  stilde(g, p->Ls, p->mass, in, out, dagger);
+  const long V12 = g.V * 12, n = V12 * p->Ls;
+  if (!dagger) {
+    stilde(g, p->Ls, p->mass, in, out, 0);
 #pragma omp parallel for schedule(static)
-  for (long k = 0; k < n; ++k) out[k] = p->b * in[k] + p->c * out[k];
+    for (long k = 0; k < n; ++k) out[k] = bco(p, int(k / V12)) * in[k] + cco(p, int(k / V12)) * out[k];
+  } else {
+    std::vector<cplx> t(n);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) t[k] = cco(p, int(k / V12)) * in[k];
+    stilde(g, p->Ls, p->mass, t.data(), out, 1);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) out[k] += bco(p, int(k / V12)) * in[k];
+  }
 }
 
 // hop on every s-slice: H (or H^dag) applied slice by slice

@@ -561,3 +561,72 @@ def test_random_momenta_distribution(ora):
     c = -2 * np.einsum("aij,nji->na", T, P).real
     cov = np.cov(c.T)
     assert np.max(np.abs(cov - np.eye(8))) < 0.06
+
+
+# --------------------------------------------------------------------- s-dependent Moebius coefficients
+def mask(psi, dims, parity):
+    """psi restricted to one 4D parity (the other parity set to zero)."""
+    keep = synth.parity_array(dims) == parity
+    return psi * keep[None, ..., None, None]
+
+
+def test_s_dependent_coefficients_constant_arrays_match_scalars(ora):
+    """Arrays b_s = b, c_s = c reproduce the constant-coefficient operator exactly."""
+    dims, Ls = (2, 2, 2, 4), 6
+    U = synth.random_links(dims, 0.5, 191)
+    psi = synth.gaussian_spinor(dims, Ls, 192)
+    p0 = ora.params(dims, Ls, mass=0.07, b=1.5, c=0.5, tbc=1)
+    p1 = ora.params(dims, Ls, mass=0.07, b=9.0, c=-3.0, tbc=1, bs=np.full(Ls, 1.5), cs=np.full(Ls, 0.5))
+    for dag in (False, True):
+        assert np.max(np.abs(ora.dwf(p0, U, psi, dagger=dag) - ora.dwf(p1, U, psi, dagger=dag))) == 0.0
+    po = mask(psi, dims, 1)
+    assert np.max(np.abs(ora.mprec(p0, U, po) - ora.mprec(p1, U, po))) < 1e-14
+
+
+def test_s_dependent_coefficients_adjoints(ora):
+    """<phi, D psi> = <D^dag phi, psi> and the same for M_prec with varying b_s, c_s (the
+    adjoint of diag(c) S~ is S~^dag diag(c): the order matters once c varies)."""
+    dims, Ls = (2, 2, 2, 4), 6
+    rng = np.random.default_rng(193)
+    bs, cs = 1.0 + rng.random(Ls), rng.random(Ls) - 0.3
+    p = ora.params(dims, Ls, mass=0.07, tbc=1, bs=bs, cs=cs)
+    U = synth.random_links(dims, 0.5, 194)
+    psi, phi = synth.gaussian_spinor(dims, Ls, 195), synth.gaussian_spinor(dims, Ls, 196)
+    lhs = np.vdot(phi, ora.dwf(p, U, psi))
+    rhs = np.vdot(ora.dwf(p, U, phi, dagger=True), psi)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    po, fo = mask(psi, dims, 1), mask(phi, dims, 1)
+    lhs = np.vdot(fo, ora.mprec(p, U, po))
+    rhs = np.vdot(ora.mprec(p, U, fo, dagger=True), po)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_s_dependent_overlap_structure(ora, dense_setup):
+    """Sec. 4 with an s-dependent Moebius operator, b_s - c_s = 1 and omega_s = b_s + c_s:
+    P^-1 D(1)^-1 D(m) P is the identity beyond its first block column, whose first block is
+    D_OV(m) = (1+m)/2 + (1-m)/2 gamma5 eps(H), eps(H) = [prod(1 + omega_s H) - prod(1 - omega_s H)]
+    [prod(1 + omega_s H) + prod(1 - omega_s H)]^-1, H = gamma5 D_W (2 + D_W)^-1."""
+    dims, _, U = dense_setup
+    Ls, m, M5 = 4, 0.04, 1.8
+    omega = np.array([0.6, 1.3, 2.1, 0.9])
+    bs, cs = (omega + 1) / 2, (omega - 1) / 2
+    shape = (Ls, 2, 2, 2, 2, 4, 3)
+    pm = ora.params(dims, Ls, M5=M5, mass=m, bs=bs, cs=cs)
+    p1 = ora.params(dims, Ls, M5=M5, mass=1.0, bs=bs, cs=cs)
+    Dm = dense_matrix(lambda v: ora.dwf(pm, U, v), shape)
+    D1 = dense_matrix(lambda v: ora.dwf(p1, U, v), shape)
+    Pm_ = dense_matrix(lambda v: ora.P(pm, v), shape)
+    Pinv = dense_matrix(lambda v: ora.P(pm, v, inverse=True), shape)
+    K = Pinv @ np.linalg.solve(D1, Dm @ Pm_)
+    n4 = 16 * 12
+    assert np.max(np.abs(K[:, n4:] - np.eye(K.shape[0])[:, n4:])) < 1e-12
+    DW = dense_dw(ora, dims, U, M5)
+    g5 = np.kron(np.kron(np.eye(16), ora.gammas()[4]), np.eye(3))
+    I = np.eye(DW.shape[0])
+    H = g5 @ DW @ np.linalg.inv(2 * I + DW)
+    Pp, Pm = I.copy(), I.copy()
+    for w in omega:
+        Pp, Pm = Pp @ (I + w * H), Pm @ (I - w * H)
+    eps = (Pp - Pm) @ np.linalg.inv(Pp + Pm)
+    DOV = 0.5 * (1 + m) * I + 0.5 * (1 - m) * g5 @ eps
+    assert np.max(np.abs(K[:n4, :n4] - DOV)) < 1e-12
