@@ -81,6 +81,12 @@ typedef struct {
   double b, c;    /* Moebius coefficients (Shamir: 1, 0) */
   int prec;       /* storage precision of packed operands of dslash calls */
   int prec_inner; /* inner-iteration precision of solvers (FP64 = plain FP64 CG) */
+  /* optional s-dependent Moebius coefficients b_s, c_s (Sec. 4 admits any Moebius
+   * operator): host arrays of Ls entries each, read during the call; NULL = the
+   * constants b, c.  (D psi)_s = (b_s D_W + 1) psi_s + (c_s D_W - 1)(P- psi_{s+1} + P+ psi_{s-1}).
+   * Not accepted by the batched solvers (cg_ne_batched, quotient_force). */
+  const double* b_s;
+  const double* c_s;
 } dwf_params;
 
 typedef struct {

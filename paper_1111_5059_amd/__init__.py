@@ -9,6 +9,8 @@ Method: Yin & Mawhinney, "Improving DWF Simulations: the Force Gradient
 Integrator and the Moebius Accelerated DWF Solver", Lattice 2011 (Secs. 2, 4, 5).
 """
 import ctypes
+
+import numpy as np
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +33,8 @@ class DwfError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int * 4), ("Ls", ctypes.c_int), ("tbc", ctypes.c_int),
                 ("M5", ctypes.c_double), ("mass", ctypes.c_double), ("b", ctypes.c_double),
-                ("c", ctypes.c_double), ("prec", ctypes.c_int), ("prec_inner", ctypes.c_int)]
+                ("c", ctypes.c_double), ("prec", ctypes.c_int), ("prec_inner", ctypes.c_int),
+                ("b_s", ctypes.c_void_p), ("c_s", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -133,13 +136,24 @@ def _ptr(t):
     return t.data_ptr()
 
 
-def params(dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0, prec=FP64, prec_inner=FP64):
+def params(dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0, prec=FP64, prec_inner=FP64, b_s=None, c_s=None):
+    """Operator parameters; b_s, c_s (optional, Ls values each): s-dependent Moebius
+    coefficients (host arrays kept alive with the parameter block)."""
     p = Params()
     for k in range(4):
         p.dims[k] = int(dims[k])
     p.Ls, p.tbc = int(Ls), int(tbc)
     p.M5, p.mass, p.b, p.c = float(M5), float(mass), float(b), float(c)
     p.prec, p.prec_inner = int(prec), int(prec_inner)
+    keep = []
+    for name, arr in (("b_s", b_s), ("c_s", c_s)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64)
+            if a.shape != (int(Ls),):
+                raise ValueError(f"{name} must hold Ls values")
+            keep.append(a)
+            setattr(p, name, a.ctypes.data)
+    p._keep = keep
     return p
 
 

@@ -257,13 +257,15 @@ int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, doubl
 template <typename P>
 __global__ void __launch_bounds__(256) cg_pupdate_f_kernel(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp,
                                                             double beta, double* scalars, double rr_new, long n5,
-                                                            int Ls, double fb, double fc, double fm) {
+                                                            int Ls, double fb0, double fc0, double fm,
+                                                            const typename P::R* bs, const typename P::R* cs) {
   using R = typename P::R;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) scalars[S_RR] = rr_new;
   if (i >= n5) return;
   const long xs = i / Ls;
   const int s = int(i - xs * Ls);
+  const double fb = bs ? double(bs[s]) : fb0, fc = cs ? double(cs[s]) : fc0;  // coefficients of slice s
   int su = s - 1, sl = s + 1;
   R fu = R(fc), fl = R(fc);
   if (su < 0) { su = Ls - 1; fu = R(-fc * fm); }
@@ -298,11 +300,12 @@ __global__ void __launch_bounds__(256) cg_pupdate_f_kernel(CHalf<P> r, CHalf<P> 
 
 template <typename P>
 int launch_cg_pupdate_f(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp, double beta, double* scalars,
-                        double rr_new, long n5, int Ls, double b, double c, double m, hipStream_t st) {
+                        double rr_new, long n5, int Ls, double b, double c, double m, hipStream_t st,
+                        const typename P::R* bs, const typename P::R* cs) {
   if (n5 <= 0) return 0;
   if (pin.data == pout.data || (beta != 0.0 && !pin.data)) return -1;
   hipLaunchKernelGGL((cg_pupdate_f_kernel<P>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, r, pin, pout,
-                     fp, beta, scalars, rr_new, n5, Ls, b, c, m);
+                     fp, beta, scalars, rr_new, n5, Ls, b, c, m, bs, cs);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -491,7 +494,7 @@ int launch_convert_links(const typename Pi::S* in, typename Po::S* out, long n, 
   template int launch_axpby<P>(double, CHalf<P>, double, Half<P>, long, int, hipStream_t);                        \
   template int launch_cg_pupdate<P>(CHalf<P>, Half<P>, double, double*, double, long, int, hipStream_t);        \
   template int launch_cg_pupdate_f<P>(CHalf<P>, CHalf<P>, Half<P>, Half<P>, double, double*, double, long, int,   \
-                                      double, double, double, hipStream_t);                                     \
+                                      double, double, double, hipStream_t, const P::R*, const P::R*);           \
   template int launch_pack_gauge<P>(const GeomTables&, const double2*, P::S*, hipStream_t);                      \
   template int launch_pack_half<P>(const GeomTables&, int, int, const double2*, Half<P>, hipStream_t);           \
   template int launch_unpack_half<P>(const GeomTables&, int, int, CHalf<P>, double2*, hipStream_t);              \

@@ -44,6 +44,12 @@ int check_params(const dwf_params* p, bool need_solver = false) {
     return fail(DWF_ERR_ARG, "unknown inner precision");
   if (!std::isfinite(p->M5) || !std::isfinite(p->mass) || !std::isfinite(p->b) || !std::isfinite(p->c))
     return fail(DWF_ERR_ARG, "non-finite operator parameter");
+  for (int s = 0; s < p->Ls; ++s) {
+    if ((p->b_s && !std::isfinite(p->b_s[s])) || (p->c_s && !std::isfinite(p->c_s[s])))
+      return fail(DWF_ERR_ARG, "non-finite s-dependent Moebius coefficient");
+    const double bb = p->b_s ? p->b_s[s] : p->b;
+    if (std::fabs(bb * (4.0 - p->M5) + 1.0) < 1e-12) return fail(DWF_ERR_ARG, "b_s (4 - M5) + 1 = 0: singular A");
+  }
   const double V = double(p->dims[0]) * p->dims[1] * p->dims[2] * p->dims[3];
   if (8.0 * V >= 2147483648.0) return fail(DWF_ERR_ARG, "lattice volume too large");
   return DWF_OK;
@@ -156,6 +162,8 @@ int dslash_any(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in,
   if (!moebius) {
     q.b = 1.0;
     q.c = 0.0;
+    q.b_s = nullptr;
+    q.c_s = nullptr;
   }
   return guarded([&]() {
     switch (q.prec) {
@@ -335,6 +343,8 @@ int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void*
     if (!U[k] || !b[k] || !x[k]) return fail(DWF_ERR_ARG, "NULL pointer in the batch");
     if (b[k] == x[k]) return fail(DWF_ERR_ARG, "b and x must not alias");
     if (!(info[k].tol > 0.0)) return fail(DWF_ERR_ARG, "tol must be positive");
+    if (per_rhs[k].b_s || per_rhs[k].c_s)
+      return fail(DWF_ERR_ARG, "s-dependent Moebius coefficients are not supported by the batched solver");
     if (per_rhs[k].M5 != per_rhs[0].M5 || per_rhs[k].b != per_rhs[0].b || per_rhs[k].c != per_rhs[0].c ||
         per_rhs[k].tbc != per_rhs[0].tbc || per_rhs[k].prec_inner != per_rhs[0].prec_inner)
       return fail(DWF_ERR_ARG, "batched right-hand sides must share M5, b, c, tbc and prec_inner");
@@ -368,6 +378,8 @@ int mobius_accel_solve(dwf_ctx* ctx, const dwf_params* target, const dwf_params*
     dwf_params t = *target;
     t.b = 1.0;
     t.c = 0.0;
+    t.b_s = nullptr;
+    t.c_s = nullptr;
     const int st = madwf(ctx, t, *inner, U, b, x, info);
     return st == 0 ? DWF_OK : DWF_NOT_CONVERGED;
   });
@@ -401,6 +413,8 @@ int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* mass
   int rc = check_params(p, true);
   if (rc) return rc;
   if (nq < 1 || nq > 64) return fail(DWF_ERR_ARG, "nq must be in 1..64");
+  if (p->b_s || p->c_s)
+    return fail(DWF_ERR_ARG, "s-dependent Moebius coefficients are not supported by the batched solver");
   if (!masses || !U || !phi || !F) return fail(DWF_ERR_ARG, "NULL pointer");
   for (int i = 0; i < nq; ++i)
     if (!phi[i]) return fail(DWF_ERR_ARG, "NULL pseudofermion");

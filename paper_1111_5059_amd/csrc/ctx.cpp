@@ -260,7 +260,7 @@ bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, Fifth
       case E_F: q.a1 = b; q.b1 = c; q.d1 = dS; break;
       case E_FDAG: q.a1 = b; q.b1 = c; q.d1 = -dS; break;
       case E_AINVDAG_FDAG: q.a1 = b; q.b1 = c; q.d1 = -dS; q.has_inv = 1; q.d2 = -dS; break;
-      case E_AINV_F: q.a1 = b; q.b1 = c; q.d1 = dS; q.has_inv = 1; q.d2 = dS; break;
+      case E_F_AINV: q.a1 = b; q.b1 = c; q.d1 = dS; q.has_inv = 1; q.d2 = dS; break;
       default: return false;
     }
     e.ch[ch] = q;
@@ -269,36 +269,96 @@ bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, Fifth
   return true;
 }
 
-const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec) {
-  char key[256];
-  snprintf(key, sizeof(key), "%d|%.17g|%.17g|%.17g|%.17g|%d", Ls, M5, m, b, c, prec == 0 ? 0 : 1);
+// inverse of a dense n x n matrix by Gauss-Jordan elimination with partial pivoting
+static std::vector<double> invert_dense(std::vector<double> M, int n) {
+  std::vector<double> I(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r * n + c]) > std::fabs(M[piv * n + c])) piv = r;
+    if (std::fabs(M[piv * n + c]) < 1e-300) throw Error{DWF_ERR_ARG, "singular fifth-dimension block A"};
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(M[c * n + k], M[piv * n + k]);
+        std::swap(I[c * n + k], I[piv * n + k]);
+      }
+    const double inv = 1.0 / M[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      M[c * n + k] *= inv;
+      I[c * n + k] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = M[r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        M[r * n + k] -= f * M[c * n + k];
+        I[r * n + k] -= f * I[c * n + k];
+      }
+    }
+  }
+  return I;
+}
+
+// Table layout: [slot][chirality][Ls][Ls] matrices, then the Moebius coefficients b_s, c_s
+// (2 Ls values; the constants repeated when not s-dependent), in the storage's real type.
+// With s-dependent coefficients A = diag(alpha_s) + diag(beta_s) S and F = diag(b_s) + diag(c_s) S
+// (row s carries the coefficients of slice s), and A^-1 is computed numerically.
+const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec,
+                           const double* bs, const double* cs) {
+  std::string key;
+  {
+    char head[160];
+    snprintf(head, sizeof(head), "%d|%.17g|%.17g|%.17g|%.17g|%d", Ls, M5, m, b, c, prec == 0 ? 0 : 1);
+    key = head;
+    char v[40];
+    for (int s = 0; bs && s < Ls; ++s) { snprintf(v, sizeof(v), "|b%.17g", bs[s]); key += v; }
+    for (int s = 0; cs && s < Ls; ++s) { snprintf(v, sizeof(v), "|c%.17g", cs[s]); key += v; }
+  }
   auto it = ctx->emats.find(key);
   if (it != ctx->emats.end()) return it->second.first;
   const int n = Ls;
+  const bool sdep = bs || cs;
+  std::vector<double> bv(n), cv(n);
+  for (int s = 0; s < n; ++s) {
+    bv[s] = bs ? bs[s] : b;
+    cv[s] = cs ? cs[s] : c;
+  }
   const double d = 4.0 - M5, alpha = b * d + 1.0, beta = c * d - 1.0;
-  if (std::fabs(alpha) < 1e-14) throw Error{DWF_ERR_ARG, "b (4 - M5) + 1 = 0: A is not invertible by the closed form"};
-  const double z = beta / alpha;
-  const double denom = alpha * (1.0 + m * std::pow(-z, Ls));
+  if (!sdep && std::fabs(alpha) < 1e-14)
+    throw Error{DWF_ERR_ARG, "b (4 - M5) + 1 = 0: A is not invertible by the closed form"};
+  const double z = sdep ? 0.0 : beta / alpha;
+  const double denom = sdep ? 1.0 : alpha * (1.0 + m * std::pow(-z, Ls));
   if (std::fabs(denom) < 1e-300) throw Error{DWF_ERR_ARG, "singular fifth-dimension block A"};
-  std::vector<double> table(size_t(E_COUNT) * 2 * n * n, 0.0);
+  std::vector<double> table(size_t(E_COUNT) * 2 * n * n + 2 * n, 0.0);
+  for (int s = 0; s < n; ++s) {
+    table[size_t(E_COUNT) * 2 * n * n + s] = bv[s];
+    table[size_t(E_COUNT) * 2 * n * n + n + s] = cv[s];
+  }
   for (int ch = 0; ch < 2; ++ch) {
     const std::vector<double> S = shift_matrix(Ls, m, ch);
     std::vector<double> I(size_t(n) * n, 0.0);
     for (int s = 0; s < n; ++s) I[s * n + s] = 1.0;
     std::vector<double> A(size_t(n) * n), F(size_t(n) * n), Ainv(size_t(n) * n, 0.0), Sk = I;
     for (int k = 0; k < n * n; ++k) {
-      A[k] = alpha * I[k] + beta * S[k];
-      F[k] = b * I[k] + c * S[k];
+      const int row = k / n;
+      A[k] = (bv[row] * d + 1.0) * I[k] + (cv[row] * d - 1.0) * S[k];
+      F[k] = bv[row] * I[k] + cv[row] * S[k];
     }
-    double coef = 1.0 / denom;
-    for (int k = 0; k < Ls; ++k) {
-      for (int q = 0; q < n * n; ++q) Ainv[q] += coef * Sk[q];
-      Sk = matmul(Sk, S, n);
-      coef *= -z;
+    if (sdep) {
+      Ainv = invert_dense(A, n);
+    } else {
+      double coef = 1.0 / denom;
+      for (int k = 0; k < Ls; ++k) {
+        for (int q = 0; q < n * n; ++q) Ainv[q] += coef * Sk[q];
+        Sk = matmul(Sk, S, n);
+        coef *= -z;
+      }
     }
     const std::vector<double> Adag = transpose(A, n), Ainvdag = transpose(Ainv, n), Fdag = transpose(F, n);
-    const std::vector<double> AinvdagFdag = matmul(Ainvdag, Fdag, n), AinvF = matmul(Ainv, F, n);
-    const std::vector<double>* mats[E_COUNT] = {&A, &Adag, &Ainv, &Ainvdag, &F, &Fdag, &AinvdagFdag, &AinvF};
+    const std::vector<double> AinvdagFdag = matmul(Ainvdag, Fdag, n), FAinv = matmul(F, Ainv, n);
+    const std::vector<double>* mats[E_COUNT] = {&A, &Adag, &Ainv, &Ainvdag, &F, &Fdag, &AinvdagFdag, &FAinv};
     for (int e = 0; e < E_COUNT; ++e)
       std::memcpy(&table[(size_t(e) * 2 + ch) * n * n], mats[e]->data(), sizeof(double) * n * n);
   }

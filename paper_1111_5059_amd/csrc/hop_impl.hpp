@@ -55,15 +55,16 @@ __device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, c
     const int Ls = a.Ls;
     cx<R> up[6], lo[6];
     int su = s - 1, sl = s + 1;
-    R fu = a.pc, fl = a.pc;
-    if (su < 0) { su = Ls - 1; fu = -a.pc * a.pm; }
-    if (sl >= Ls) { sl = 0; fl = -a.pc * a.pm; }
+    const R pb = a.pbs ? a.pbs[s] : a.pb, pc = a.pcs ? a.pcs[s] : a.pc;  // coefficients of slice s
+    R fu = pc, fl = pc;
+    if (su < 0) { su = Ls - 1; fu = -pc * a.pm; }
+    if (sl >= Ls) { sl = 0; fl = -pc * a.pm; }
     load_half_spinor<P>(a.in, y, su, Ls, 0, up);  // P+ (spins 0,1) picks psi_{s-1}
     load_half_spinor<P>(a.in, y, sl, Ls, 6, lo);  // P- (spins 2,3) picks psi_{s+1}
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      psi[k] = a.pb * psi[k] + fu * up[k];
-      psi[6 + k] = a.pb * psi[6 + k] + fl * lo[k];
+      psi[k] = pb * psi[k] + fu * up[k];
+      psi[6 + k] = pb * psi[6 + k] + fl * lo[k];
     }
   }
 }
@@ -173,10 +174,11 @@ __device__ __forceinline__ float load_input_f16_pro(const HopArgs<P16>& a, long 
   const __half2* p = a.in.data + size_t(y) * 12 * Ls;
   const float* nb = a.in.norm + size_t(y) * Ls;
   int su = s - 1, sl = s + 1;
-  float fu = a.pc, fl = a.pc;
-  if (su < 0) { su = Ls - 1; fu = -a.pc * a.pm; }
-  if (sl >= Ls) { sl = 0; fl = -a.pc * a.pm; }
-  const float ws = a.pb * nb[s], wu = fu * nb[su], wl = fl * nb[sl];
+  const float pb = a.pbs ? a.pbs[s] : a.pb, pc = a.pcs ? a.pcs[s] : a.pc;  // coefficients of slice s
+  float fu = pc, fl = pc;
+  if (su < 0) { su = Ls - 1; fu = -pc * a.pm; }
+  if (sl >= Ls) { sl = 0; fl = -pc * a.pm; }
+  const float ws = pb * nb[s], wu = fu * nb[su], wl = fl * nb[sl];
   const float m = fmaxf(fabsf(ws), fmaxf(fabsf(wu), fabsf(wl)));
   const float inv = m > 1e-37f ? __builtin_amdgcn_rcpf(m) : 0.0f;  // (ratios only need FP16 accuracy)
   const _Float16 hs = (_Float16)(ws * inv), hu = (_Float16)(wu * inv), hl = (_Float16)(wl * inv);

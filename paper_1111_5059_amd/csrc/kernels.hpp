@@ -36,6 +36,8 @@ struct HopArgs {
   int Ls;
   typename P::R scale;
   typename P::R pb, pc, pm;    // prologue F = pb + pc S~, boundary factor -pm
+  const typename P::R* pbs = nullptr;  // s-dependent prologue coefficients b_s, c_s (device, Ls
+  const typename P::R* pcs = nullptr;  // each; nullptr: the constants pb, pc)
   const typename P::R* E;      // epilogue [2][Ls][Ls] or nullptr
   FifthScan<typename P::R> es; // the same epilogue in recurrence form
   int epi_scan;                // es is valid (used when the site's lanes form a wave segment)
@@ -99,7 +101,8 @@ int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, doubl
 // p_out = r + beta p_in (p_in unused when beta = 0) and fp = (b + c S~) p_out, rr_new -> S_RR
 template <typename P>
 int launch_cg_pupdate_f(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp, double beta, double* scalars,
-                        double rr_new, long n5, int Ls, double b, double c, double m, hipStream_t st);
+                        double rr_new, long n5, int Ls, double b, double c, double m, hipStream_t st,
+                        const typename P::R* bs = nullptr, const typename P::R* cs = nullptr);
 // P / P^-1 of the domain-wall <-> overlap transformation on an FP64 half field
 int launch_pshift(CHalf<P64> in, Half<P64> out, int inverse, long nsites, int Ls, hipStream_t st);
 // out(s_out) = scale * in(s_in) on FP64 half fields of extents Ls_in, Ls_out

@@ -101,7 +101,9 @@ void* ws_get(dwf_ctx* ctx, const std::string& name, size_t bytes);
 const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc);
 LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls);
 // device buffer of the fifth-dimension matrices for one parameter set
-const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec);
+// (bs, cs: optional s-dependent Moebius coefficients, Ls entries each)
+const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec,
+                           const double* bs = nullptr, const double* cs = nullptr);
 double read_scalar(dwf_ctx* ctx, const double* dscalars, int slot);
 // timer marks around one launch (no-ops while timing is off); begin returns the mark index or -1
 long timer_begin(dwf_ctx* ctx, const std::string& kernel);
@@ -118,8 +120,9 @@ inline const char* prec_tag(int id) {
 }
 
 // slots of the per-parameter fifth-dimension matrix table ([slot][2][Ls][Ls])
-// (A^-1 F = F A^-1: per chirality both are functions of the same shift)
-enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_AINV_F, E_COUNT };
+// (E_F_AINV = F A^-1; with constant coefficients F and A^-1 commute, per chirality both
+// being functions of one shift, which the recurrence form uses)
+enum EMat { E_A = 0, E_ADAG, E_AINV, E_AINVDAG, E_F, E_FDAG, E_AINVDAG_FDAG, E_F_AINV, E_COUNT };
 bool fifth_scan(int Ls, double M5, double m, double b, double c, int slot, FifthScan<double>* out);
 
 template <typename P>
@@ -146,22 +149,29 @@ struct Op {
   int Ls;
   double M5, m, b, c;
   bool moebius;  // F != 1
+  bool sdep;     // s-dependent Moebius coefficients
   const S* U[2];
   const R* E;
+  const R* coef_b;  // device b_s, c_s (Ls each), in the table after the matrices
+  const R* coef_c;
   FifthScan<R> es[E_COUNT];  // the slots in recurrence form
   bool scan_ok;
   LaunchCfg cfg;
 
   Op(dwf_ctx* ctx_, const Geometry* g_, const dwf_params& p, const void* packed_links)
       : ctx(ctx_), g(g_), Ls(p.Ls), M5(p.M5), m(p.mass), b(p.b), c(p.c) {
-    moebius = !(b == 1.0 && c == 0.0);
+    sdep = p.b_s || p.c_s;
+    moebius = sdep || !(b == 1.0 && c == 0.0);
     const S* base = reinterpret_cast<const S*>(packed_links);
     U[0] = base;
     U[1] = base + size_t(g->nsites) * 72;
-    E = reinterpret_cast<const R*>(fifth_matrices(ctx, Ls, M5, m, b, c, P::ID));
+    E = reinterpret_cast<const R*>(fifth_matrices(ctx, Ls, M5, m, b, c, P::ID, p.b_s, p.c_s));
+    coef_b = E + size_t(E_COUNT) * 2 * Ls * Ls;
+    coef_c = coef_b + Ls;
     cfg = hop_config(ctx, P::ID, Ls);
-    scan_ok = true;
-    for (int slot = 0; slot < E_COUNT; ++slot) {
+    // the recurrence (scan) form assumes constant coefficients: dense epilogues otherwise
+    scan_ok = !sdep;
+    for (int slot = 0; scan_ok && slot < E_COUNT; ++slot) {
       FifthScan<double> e;
       if (!fifth_scan(Ls, M5, m, b, c, slot, &e)) { scan_ok = false; break; }
       es[slot].m = R(e.m);
@@ -206,6 +216,10 @@ struct Op {
     a.pb = R(b);
     a.pc = R(c);
     a.pm = R(m);
+    if (sdep) {
+      a.pbs = coef_b;
+      a.pcs = coef_c;
+    }
     a.E = epi;
     a.epi_scan = 0;
     if (epi && scan_ok) {
@@ -257,10 +271,10 @@ struct Op {
     hop(1, cv(tmp_e), out, false, true, -0.25, em(E_AINV), in, 1.0, partials, CgStep(), ainvdag_out, E_AINVDAG);
   }
   // M_prec psi from fpsi = F psi prepared by the caller (the CG p update): both hops without
-  // the input factor, the first with the epilogue A^-1 F = F A^-1 (Moebius operators)
+  // the input factor, the first with the epilogue F A^-1 (Moebius operators)
   void mprec_pre(CHalf<P> fin, CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr,
                  Half<P> ainvdag_out = {nullptr, nullptr}) const {
-    hop(0, fin, tmp_e, false, false, 1.0, em(E_AINV_F));
+    hop(0, fin, tmp_e, false, false, 1.0, em(E_F_AINV));
     hop(1, cv(tmp_e), out, false, false, -0.25, em(E_AINV), in, 1.0, partials, CgStep(), ainvdag_out, E_AINVDAG);
   }
   // M_prec^dag psi = psi - 1/4 F^dag H^dag_oe (A^-dag F^dag) H^dag_eo A^-dag psi

@@ -113,7 +113,8 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   Half<Pi> fp = PRE ? hview<Pi>(ws_get(ctx, tag + ".fp." + pname(Pi::ID), hbi), g, Ls) : Half<Pi>{nullptr, nullptr};
   auto p_update = [&](double beta, double rr_new) {
     if (PRE) {
-      DWF_CHECK_LAUNCH(launch_cg_pupdate_f<Pi>(cv(r), cv(p), p2, fp, beta, sc, rr_new, n5, Ls, opi.b, opi.c, opi.m, s));
+      DWF_CHECK_LAUNCH(launch_cg_pupdate_f<Pi>(cv(r), cv(p), p2, fp, beta, sc, rr_new, n5, Ls, opi.b, opi.c, opi.m, s,
+                                               opi.sdep ? opi.coef_b : nullptr, opi.sdep ? opi.coef_c : nullptr));
       std::swap(p, p2);
     } else {
       DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, beta, sc, rr_new, n5, Ls, s));

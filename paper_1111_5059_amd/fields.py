@@ -18,19 +18,24 @@ def _torch():
 class Lattice:
     """One 4D lattice and fifth-dimension extent with its operator parameters."""
 
-    def __init__(self, ctx, dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0, device="cuda"):
+    def __init__(self, ctx, dims, Ls, M5=1.8, mass=0.01, b=1.0, c=0.0, tbc=0, device="cuda", b_s=None, c_s=None):
         self.ctx, self.dims, self.Ls = ctx, tuple(int(d) for d in dims), int(Ls)
         self.M5, self.mass, self.b, self.c, self.tbc = float(M5), float(mass), float(b), float(c), int(tbc)
+        self.b_s = None if b_s is None else np.asarray(b_s, dtype=np.float64)
+        self.c_s = None if c_s is None else np.asarray(c_s, dtype=np.float64)
         self.device = device
 
     def params(self, prec=FP64, prec_inner=FP64, **kw):
         d = dict(dims=self.dims, Ls=self.Ls, M5=self.M5, mass=self.mass, b=self.b, c=self.c, tbc=self.tbc,
-                 prec=prec, prec_inner=prec_inner)
+                 prec=prec, prec_inner=prec_inner, b_s=self.b_s, c_s=self.c_s)
         d.update(kw)
         return params(**d)
 
     def with_(self, **kw):
-        d = dict(dims=self.dims, Ls=self.Ls, M5=self.M5, mass=self.mass, b=self.b, c=self.c, tbc=self.tbc)
+        d = dict(dims=self.dims, Ls=self.Ls, M5=self.M5, mass=self.mass, b=self.b, c=self.c, tbc=self.tbc,
+                 b_s=self.b_s, c_s=self.c_s)
+        if "Ls" in kw and "b_s" not in kw and "c_s" not in kw:
+            d["b_s"] = d["c_s"] = None  # coefficient arrays belong to one fifth-dimension extent
         d.update(kw)
         return Lattice(self.ctx, device=self.device, **d)
 
