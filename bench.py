@@ -199,6 +199,42 @@ def fgi_measure(dwf, ctx, prec="fp32", tol=1e-8, n_steps=2, tau=0.1, beta=5.7, e
             "fg_iters_first": info["fg_iters_first"], "fg_iters_forecast": info["fg_iters_forecast"]}
 
 
+def sdep_measure(dwf, ctx, lat, U64, prec="fp16", reps=10):
+    """M_prec^dag M_prec of the Moebius inner operator (Ls' = 16) on the benchmark lattice with
+    constant b = 1.5, c = 0.5 and with s-dependent b_s, c_s (b_s - c_s = 1, b_s + c_s spread
+    around 2): the s-dependent operator takes the dense fifth-dimension epilogues."""
+    import torch
+    P = dwf.PREC_NAMES[prec]
+    Lp = 16
+    omega = 2.0 + 0.5 * np.sin(np.arange(Lp))
+    out = {}
+    for label, lt in (("constant", lat.with_(Ls=Lp, b=1.5, c=0.5)),
+                      ("s_dependent", lat.with_(Ls=Lp, b_s=(omega + 1) / 2, c_s=(omega - 1) / 2))):
+        Ug = lt.empty(dwf.KIND_GAUGE, P)
+        dwf.dwf_convert(ctx, lt.params(P), dwf.KIND_GAUGE, dwf.FP64, U64, P, Ug)
+        tmp = lt.zeros(dwf.KIND_ODD, dwf.FP64)
+        rng = torch.Generator(device="cuda")
+        rng.manual_seed(13)
+        tmp.view(torch.float64).normal_(generator=rng)
+        a = lt.empty(dwf.KIND_ODD, P)
+        dwf.dwf_convert(ctx, lt.params(P), dwf.KIND_ODD, dwf.FP64, tmp, P, a)
+        bb = lt.empty(dwf.KIND_ODD, P)
+        p = lt.params(P)
+        for _ in range(2):
+            dwf.mobius_dslash(ctx, p, Ug, a, bb, dwf.OP_MPREC, 1, False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            dwf.mobius_dslash(ctx, p, Ug, a, bb, dwf.OP_MPREC, 1, False)
+            dwf.mobius_dslash(ctx, p, Ug, bb, a, dwf.OP_MPREC, 1, True)
+        torch.cuda.synchronize()
+        out[label + "_ms"] = (time.perf_counter() - t) / reps * 1e3
+        del Ug, tmp, a, bb
+    out["workload"] = (f"M_prec^dag M_prec, Moebius 24^3x64 Ls'=16 m=0.005, {prec} storage: constant b=1.5, c=0.5 "
+                       f"vs s-dependent b_s - c_s = 1, b_s + c_s = 2 + 0.5 sin(s)")
+    return out
+
+
 def cpu_baseline(workload, U, b_nat, fp64_iters, seconds_budget=25.0):
     """FP64 oracle on the host cores: time M_prec^dag M_prec on the same operator,
     restricted to a bounded sample (one or more applications on the workload's lattice
@@ -356,6 +392,12 @@ def main():
             f"(ratio {fgi['dH_ratio']:.1f}), forecast solves {fgi['fg_iters_forecast']} vs "
             f"{fgi['fg_iters_first']} iterations")
 
+    sdep = None
+    if not args.no_extras:
+        sdep = sdep_measure(dwf, ctx, lat, U64)
+        log(f"Moebius M^dag M (fp16): constant coefficients {sdep['constant_ms']:.2f} ms, s-dependent "
+            f"{sdep['s_dependent_ms']:.2f} ms")
+
     cpu = None
     if not args.no_cpu_baseline and fp64 is not None:
         log("CPU oracle baseline ...")
@@ -403,6 +445,7 @@ def main():
         "cpu_baseline": cpu,
         "hasenbusch_ladder": ladder,
         "fgi_trajectory": fgi,
+        "s_dependent_moebius": sdep,
         "paper_context": "Table 1 (BG/P, 512 nodes, 32^3x64, L=32 -> L'=12): 1.8x fewer 4D Wilson "
                          "applications, 42% of the direct-CG wall time",
     }
