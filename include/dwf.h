@@ -241,11 +241,13 @@ int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* mass
 
 /* Set / query the launch configuration of the hop kernels for one (precision,
  * Ls): 4D sites per workgroup, s-slices per thread, whether workgroups are
- * remapped so that each XCD walks a contiguous range of the lattice, and
- * whether the workgroup's links are staged in LDS.  Used by the autotuner;
+ * remapped so that each XCD walks a contiguous range of the lattice, and the
+ * LDS mode link_lds: 0 nothing staged, 1 the workgroup's links staged in LDS,
+ * 2 the neighbour spinors of every direction staged in LDS (FP16, Ls 8/16/32,
+ * one slice per thread, 256 / Ls sites per workgroup).  Used by the autotuner;
  * kernel_id 0 = hop.  sites_per_block = s_per_thread = 0 restores the default.
  * Rejects shapes the kernel cannot run (more than 256 threads, Ls not divisible
- * by s_per_thread, LDS above 64 KiB) with DWF_ERR_ARG. */
+ * by s_per_thread, LDS above 64 KiB, mode 2 outside its shape) with DWF_ERR_ARG. */
 int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_block, int s_per_thread,
                  int xcd_remap, int link_lds);
 int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* sites_per_block, int* s_per_thread,

@@ -3,7 +3,7 @@
 For one (precision, Ls, lattice) it times the even-odd operator M_prec (the solver's inner
 kernel mix: hops with the fused fifth-dimension epilogue, prologue and axpy) over every valid
 launch shape -- 4D sites per workgroup, s-slices per thread, XCD-aware workgroup order, links
-staged in LDS -- keeps the fastest, installs it with ``dwf_tune_set`` and caches it in a JSON
+or neighbour spinors staged in LDS -- keeps the fastest, installs it with ``dwf_tune_set`` and caches it in a JSON
 file keyed by (kernel, precision, Ls, lattice).  Shapes the kernel cannot run (more than 256
 threads, LDS above 64 KiB) are never tried: the library rejects them before launching.
 """
@@ -31,8 +31,10 @@ def candidates(prec, Ls):
             threads = spb * Ls // ns
             if threads > 256 or threads < 32:
                 continue
-            for ll in (0, 1):
-                lds = spb * 12 * Ls * elem_c + (spb * 72 * elem_s if ll else 0)
+            for ll in (0, 1, 2):  # LDS mode: none, links, neighbour spinors (FP16)
+                if ll == 2 and not (prec == 2 and ns == 1 and threads == 256 and Ls in (8, 16, 32)):
+                    continue
+                lds = spb * 12 * Ls * elem_c + (spb * 72 * elem_s if ll == 1 else 0)
                 if lds > 65536:
                     continue
                 for xcd in (0, 1):

@@ -439,14 +439,18 @@ int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns,
   if (spb < 1 || spb * (Ls / ns) > 256) return fail(DWF_ERR_ARG, "sites_per_block * Ls / s_per_thread must be <= 256");
   const size_t elem = prec == DWF_FP64 ? 16 : 8;
   const size_t lelem = prec == DWF_FP64 ? 16 : prec == DWF_FP32 ? 8 : 4;
+  if (ll < 0 || ll > 2) return fail(DWF_ERR_ARG, "lds mode must be 0, 1 or 2");
+  if (ll == 2 && (prec != DWF_FP16 || ns != 1 || spb * Ls != 256 || (Ls != 8 && Ls != 16 && Ls != 32)))
+    return fail(DWF_ERR_ARG, "staged neighbour spinors need FP16, Ls 8/16/32, one slice per thread and 256 threads");
   const size_t lsite = prec == DWF_FP16 ? 160 : 72;  // FP16 links are staged in two forms
-  if (size_t(spb) * 12 * Ls * elem + (ll ? size_t(spb) * lsite * lelem : 0) > 65536)
+  if (size_t(spb) * 12 * Ls * elem + (ll == 1 ? size_t(spb) * lsite * lelem : 0) > 65536)
     return fail(DWF_ERR_ARG, "workgroup LDS (epilogue + staged links) exceeds 64 KiB");
   LaunchCfg c;
   c.spb = spb;
   c.ns = ns;
   c.xcd = xcd ? 1 : 0;
-  c.ll = ll ? 1 : 0;
+  c.ll = ll == 1 ? 1 : 0;
+  c.stage = ll == 2 ? 1 : 0;
   ctx->tune[key] = c;
   return DWF_OK;
 }
@@ -458,7 +462,7 @@ int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* spb, int* n
   *spb = c.spb;
   *ns = c.ns;
   *xcd = c.xcd;
-  *ll = c.ll;
+  *ll = stage_shape(c, Ls) ? 2 : c.ll;
   return DWF_OK;
 }
 

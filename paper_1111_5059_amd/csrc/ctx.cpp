@@ -188,6 +188,9 @@ LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls) {
   // links staged in LDS, except FP16: its links are read by every lane of a site at one
   // address (a broadcast) and the two staged forms would double the LDS footprint
   c.ll = prec == DWF_FP16 ? 0 : 1;
+  // neighbour spinors staged through LDS (LDS mode 2) only on request: at the 24^3 x 64 shapes
+  // (Ls 16, 32) the staged FP16 hops measured 1.2-1.4x slower than the per-lane gathers
+  c.stage = 0;
   int spb = 256 / Ls;
   if (spb < 1) spb = 1;
   while (spb > 1 && (spb * Ls) % 64 != 0) --spb;

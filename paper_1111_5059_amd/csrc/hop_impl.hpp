@@ -223,6 +223,87 @@ __device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const
   }
 }
 
+// ------------------------------------------------------------------ LDS-staged neighbour spinors
+// FP16 with a compile-time Ls and one slice per lane: for each direction the workgroup copies
+// the spinors of its sites' neighbours (one contiguous [12][Ls] block of half2 and Ls norms per
+// site) into LDS with global_load_lds_dwordx4 (16 bytes per lane, no registers held while the
+// copy is in flight), and the lanes then read their operands from LDS.  The per-lane gathers of
+// the plain hop are bound by their latency; the bulk copies keep many more bytes in flight.
+template <int LS>
+struct Stage {
+  static constexpr int SPINOR_CHUNKS = 12 * LS * 4 / 16;      // 16-byte chunks of one site's spinor
+  static constexpr int CHUNKS = SPINOR_CHUNKS + LS * 4 / 16;  // ... and its norms
+  static constexpr int SITE_BYTES = CHUNKS * 16;
+  static constexpr int SPB = 256 / LS;
+  static constexpr int WG_CHUNKS = SPB * CHUNKS;
+  static constexpr int ROUNDS = (WG_CHUNKS + 255) / 256;
+  static constexpr int BUF = ROUNDS * 256 * 16;               // bytes per direction buffer
+};
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// issue the copies of the nact sites' neighbours in one direction (ys[j] = neighbour x_cb);
+// chunk c lands at buf + 16 c: the lanes of one wave write consecutive 16-byte slots
+template <int LS>
+__device__ __forceinline__ void stage_dir(const HopArgs<P16>& a, const int* ys, int nact, unsigned char* buf) {
+  using G = Stage<LS>;
+  const int wave_base = threadIdx.x & ~63;
+#pragma unroll
+  for (int r = 0; r < G::ROUNDS; ++r) {
+    const int c = r * 256 + int(threadIdx.x);
+    if (c < nact * G::CHUNKS) {
+      const int j = c / G::CHUNKS;
+      const int part = c - j * G::CHUNKS;
+      const size_t y = size_t(ys[j]);
+      const char* src = part < G::SPINOR_CHUNKS
+                            ? reinterpret_cast<const char*>(a.in.data + y * 12 * LS) + part * 16
+                            : reinterpret_cast<const char*>(a.in.norm + y * LS) + (part - G::SPINOR_CHUNKS) * 16;
+      __builtin_amdgcn_global_load_lds(src, (lds_void_ptr)(buf + (r * 256 + wave_base) * 16), 16, 0, 0);
+    }
+  }
+}
+
+// one direction of the FP16 hop with the neighbour's spinor read from its staged copy sb
+template <int MU, int SG, int LS>
+__device__ __forceinline__ void hop_dir_f16_staged(const unsigned char* sb, int s, float scale, const __half2* L,
+                                                   int D, cx<float> (&acc)[1][12]) {
+  f16x2 Uc[9], Us[9];
+  links_f16<true>(L, D, Uc, Us);  // the workgroup's links, staged in LDS
+  const __half2* p = reinterpret_cast<const __half2*>(sb) + s;
+  f16x2 psi[12], h[6];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) psi[k] = as_f16x2(p[k * LS]);
+  const float n = reinterpret_cast<const float*>(sb + 48 * LS)[s] * scale;
+  project_f16<MU, SG>(psi, h);
+  float re[6], im[6];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int row = 0; row < 3; ++row) {
+      re[r * 3 + row] = row_dot(Uc[row * 3], Uc[row * 3 + 1], Uc[row * 3 + 2], h[r * 3], h[r * 3 + 1], h[r * 3 + 2]);
+      im[r * 3 + row] = row_dot(Us[row * 3], Us[row * 3 + 1], Us[row * 3 + 2], h[r * 3], h[r * 3 + 1], h[r * 3 + 2]);
+    }
+  reconstruct_fma<MU, SG>(re, im, n, acc[0]);
+}
+
+// direction D: copy the neighbours' spinors into the buffer, wait for every wave's copies,
+// compute, and release the buffer.  One buffer per workgroup (about 22 KB of LDS with the
+// staged links): several workgroups per CU are at different phases, so that copies of some
+// overlap the arithmetic of others.
+template <int D, bool DAG, int LS>
+__device__ __forceinline__ void staged_step(const HopArgs<P16>& a, const int* ys, int spb, int nact, bool active,
+                                            int lsite, int s, const __half2* L, unsigned char* buf,
+                                            cx<float> (&acc)[1][12]) {
+  constexpr int MU = D & 3;
+  constexpr bool FWD = D < 4;
+  constexpr int SG = (FWD != DAG) ? -1 : +1;
+  using G = Stage<LS>;
+  stage_dir<LS>(a, ys + D * spb, nact, buf);
+  __syncthreads();  // (waits for this wave's copies, then for every wave)
+  if (active) hop_dir_f16_staged<MU, SG, LS>(buf + lsite * G::SITE_BYTES, s, a.scale, L, D, acc);
+  __syncthreads();  // the buffer is free for the next direction
+}
+
 // One of the 8 hop directions: D = 0..3 forward (x+mu), 4..7 backward (x-mu).
 // H uses (1 - g_mu) forward and (1 + g_mu) backward; H^dag the opposite.
 // PAIRED: FP16 links staged as (U, Us) pairs, 20 elements per direction.
@@ -257,7 +338,10 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, cons
 template <typename P, bool CG>
 constexpr int hop_min_waves() { return std::is_same<P, P16>::value && !CG ? 5 : 1; }
 
-template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG>
+// ST: neighbour spinors staged through LDS (FP16, compile-time Ls, one slice per lane, no
+// prologue, spb = 256 / Ls); its links are staged too (LL), so that the direction loop issues
+// no other vector-memory loads than the copies
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST>
 __global__ void __launch_bounds__(256, (hop_min_waves<P, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -309,7 +393,29 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, CG>())) hop_kernel(HopA
   } else {
     L = a.links + x * 72;
   }
-  if (active) {
+  if constexpr (ST) {
+    static_assert(std::is_same<P, P16>::value && NS == 1 && !PRO && LL && LS > 0 && EPI != 1, "staged hop");
+    __shared__ int ys[8 * 32];  // [direction][site]: neighbour x_cb of the workgroup's sites
+    const long base = bid * spb;
+    const int nact = int(a.nsites - base < spb ? a.nsites - base : spb);
+    for (int i = threadIdx.x; i < 8 * spb; i += blockDim.x) {
+      const int j = i / 8, d = i - j * 8;
+      if (j < nact) {
+        const long xs = a.order ? long(a.order[base + j]) : base + j;
+        ys[d * spb + j] = a.nbr[xs * 8 + d];
+      }
+    }
+    __shared__ __align__(16) unsigned char sbuf[Stage<LS>::BUF];
+    __syncthreads();
+    staged_step<0, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<1, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<2, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<3, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<4, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<5, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<6, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+    staged_step<7, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
+  } else if (active) {
     const int* nb = a.nbr + x * 8;
     hop_dir<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
     hop_dir<1, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
@@ -425,18 +531,33 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, CG>())) hop_kernel(HopA
   }
 }
 
+// the staged variant applies to this instantiation and launch shape
+template <typename P, int LS, int NS, bool PRO, int EPI>
+constexpr bool stage_capable() {
+  return std::is_same<P, P16>::value && NS == 1 && !PRO && EPI != 1 && (LS == 8 || LS == 16 || LS == 32);
+}
+
 template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool CG>
 static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
   const int tps = a.Ls / NS;
   const int threads = cfg.spb * tps;
   const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
+  if constexpr (stage_capable<P, LS, NS, PRO, EPI>()) {
+    if (stage_shape(cfg, a.Ls)) {
+      LaunchCfg c2 = cfg;
+      c2.ll = 1;
+      hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true, CG, true>), dim3((unsigned)blocks),
+                         dim3(threads), hop_lds_bytes<P>(c2, a.Ls, false), st, a, cfg.spb, cfg.xcd);
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    }
+  }
   const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, EPI == 1);
   if (cfg.ll)
-    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true, CG>), dim3((unsigned)blocks), dim3(threads), lds, st,
-                       a, cfg.spb, cfg.xcd);
+    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, true, CG, false>), dim3((unsigned)blocks), dim3(threads),
+                       lds, st, a, cfg.spb, cfg.xcd);
   else
-    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, false, CG>), dim3((unsigned)blocks), dim3(threads), lds,
-                       st, a, cfg.spb, cfg.xcd);
+    hipLaunchKernelGGL((hop_kernel<P, LS, NS, DAG, PRO, EPI, false, CG, false>), dim3((unsigned)blocks),
+                       dim3(threads), lds, st, a, cfg.spb, cfg.xcd);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -57,11 +57,16 @@ struct HopArgs {
 };
 
 struct LaunchCfg {
-  int spb;  // 4D sites per block
-  int ns;   // s-values per thread
-  int xcd;  // XCD-aware block order
-  int ll;   // links staged in LDS
+  int spb;        // 4D sites per block
+  int ns;         // s-values per thread
+  int xcd;        // XCD-aware block order
+  int ll;         // links staged in LDS
+  int stage = 0;  // neighbour spinors (and links) staged through LDS (FP16, Ls 8/16/32, spb = 256/Ls, ns 1)
 };
+// the launch shape the LDS-staged hop runs with
+inline bool stage_shape(const LaunchCfg& cfg, int Ls) {
+  return cfg.stage && cfg.ns == 1 && cfg.spb * Ls == 256 && (Ls == 8 || Ls == 16 || Ls == 32);
+}
 
 template <typename P>
 int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st);

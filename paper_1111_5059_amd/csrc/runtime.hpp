@@ -246,9 +246,12 @@ struct Op {
     const int ls = (Ls == 8 || Ls == 12 || Ls == 16 || Ls == 32) ? Ls : 0;
     int epi = 0;
     if (a.E) epi = (a.epi_scan && cfg.ns == 1 && (ls == 8 || ls == 16 || ls == 32)) ? (a.out2.data ? 3 : 2) : 1;
+    const bool st = P::ID == DWF_FP16 && cfg.ns == 1 && !pro && epi != 1 && (ls == 8 || ls == 16 || ls == 32) &&
+                    stage_shape(cfg, Ls);
     return std::string("hop_kernel<") + prec_tag(P::ID) + ", " + std::to_string(ls) + ", " + std::to_string(cfg.ns) +
            ", " + (dag ? "true" : "false") + ", " + (pro ? "true" : "false") + ", " + std::to_string(epi) + ", " +
-           (cfg.ll ? "true" : "false") + ", " + (a.cg_r.data ? "true" : "false") + ">";
+           (cfg.ll || st ? "true" : "false") + ", " + (a.cg_r.data ? "true" : "false") + ", " +
+           (st ? "true" : "false") + ">";
   }
   void fifth(CHalf<P> in, Half<P> out, int slot, CHalf<P> x = {nullptr, nullptr}, double ax = 0.0,
              double* partials = nullptr) const {

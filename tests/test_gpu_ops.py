@@ -185,17 +185,18 @@ def test_kernel_timing_report(env):
     finally:
         dwf.dwf_timing_enable(ctx, False)
     spb, ns, xcd, ll = dwf.dwf_tune_get(ctx, P, Ls)
-    llb = "true" if ll else "false"
+    llb = "true" if ll in (1, 2) else "false"  # (the staged variant also stages its links)
+    st = "true" if ll == 2 else "false"
     epi = 2 if ns == 1 else 1
     nsites = 8 ** 4 // 2
     site = 12 * 4 + 4  # FP16 spinor (12 half2) + FP32 norm per 5D site
     links = nsites * 72 * 4
     want = {
         # M_prec: two hops with the A^-1 epilogue, the second with the axpy operand
-        f"hop_kernel<dwf::P16, 16, {ns}, false, false, {epi}, {llb}, false>": (2, nsites * Ls * site * 5 + 2 * links),
+        f"hop_kernel<dwf::P16, 16, {ns}, false, false, {epi}, {llb}, false, {st}>": (2, nsites * Ls * site * 5 + 2 * links),
         # M_prec^dag: A^-dag, then a dagger hop with an epilogue and one without
-        f"hop_kernel<dwf::P16, 16, {ns}, true, false, {epi}, {llb}, false>": (1, nsites * Ls * site * 2 + links),
-        f"hop_kernel<dwf::P16, 16, {ns}, true, false, 0, {llb}, false>": (1, nsites * Ls * site * 3 + links),
+        f"hop_kernel<dwf::P16, 16, {ns}, true, false, {epi}, {llb}, false, {st}>": (1, nsites * Ls * site * 2 + links),
+        f"hop_kernel<dwf::P16, 16, {ns}, true, false, 0, {llb}, false, {st}>": (1, nsites * Ls * site * 3 + links),
         "fifth_kernel<dwf::P16, 16>": (1, nsites * Ls * site * 2),
     }
     assert set(rep) == set(want), rep
