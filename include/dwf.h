@@ -253,6 +253,18 @@ int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_bl
 int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* sites_per_block, int* s_per_thread,
                  int* xcd_remap, int* link_lds);
 
+/* Set / query the traversal tile of the hop kernels on one lattice (dims[4], tbc as in
+ * dwf_params): workgroups visit the output sites in 3D tiles of tile[0] x tile[1] x tile[2]
+ * spatial sites, each tile walked along t before the next, so that the eight users of an
+ * input spinor run close together in time and its re-reads hit the L2.  Only the order of
+ * the visits changes; every result is bit-identical.  Each extent must divide the lattice
+ * extent (DWF_ERR_ARG otherwise); 0, 0, 0 restores the default: among the tiles of at most
+ * 600 sites per t-slice, the one with the smallest halo ratio (tx+2)(ty+2)(tz+2)/(tx ty tz).
+ * dwf_tune_tile waits for the context stream before it replaces the order; tile is an int[3]
+ * host array. */
+int dwf_tune_tile(dwf_ctx* ctx, const int* dims, int tbc, const int* tile);
+int dwf_tune_tile_get(dwf_ctx* ctx, const int* dims, int tbc, int* tile);
+
 /* Measurement.  dwf_timing_enable(ctx, 1) starts recording a HIP event pair on the
  * context stream around every Wilson-hop and fifth-dimension kernel launch the
  * context makes (the events add a few microseconds between launches);

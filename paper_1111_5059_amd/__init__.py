@@ -98,6 +98,8 @@ SIGNATURES = {
     "fermion_force": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(_cd), _cd, _ci, _vp, ctypes.POINTER(SolveInfo)], _ci),
     "dwf_tune_set": ([_vp, _ci, _ci, _ci, _ci, _ci, _ci, _ci], _ci),
     "dwf_tune_get": ([_vp, _ci, _ci, _ci] + [ctypes.POINTER(_ci)] * 4, _ci),
+    "dwf_tune_tile": ([_vp, ctypes.POINTER(_ci), _ci, ctypes.POINTER(_ci)], _ci),
+    "dwf_tune_tile_get": ([_vp, ctypes.POINTER(_ci), _ci, ctypes.POINTER(_ci)], _ci),
     "quotient_force": ([_vp, _PP, _ci, ctypes.POINTER(_cd), _vp, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_cd), _ci,
                         ctypes.POINTER(_vp), ctypes.POINTER(SolveInfo)], _ci),
     "hmc_fgi_trajectory": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(HmcInfo)], _ci),
@@ -304,6 +306,19 @@ def dwf_tune_get(ctx, prec, Ls, kernel_id=0):
     v = [_ci(0) for _ in range(4)]
     _check(lib().dwf_tune_get(ctx.handle, int(kernel_id), int(prec), int(Ls), *[ctypes.byref(t) for t in v]))
     return tuple(t.value for t in v)
+
+
+def dwf_tune_tile(ctx, dims, tile=(0, 0, 0), tbc=0):
+    """Traversal tile (tx, ty, tz) of the hop kernels on the lattice ``dims``; (0, 0, 0)
+    restores the default.  Results do not depend on it."""
+    d, t = (_ci * 4)(*[int(v) for v in dims]), (_ci * 3)(*[int(v) for v in tile])
+    _check(lib().dwf_tune_tile(ctx.handle, d, int(tbc), t))
+
+
+def dwf_tune_tile_get(ctx, dims, tbc=0):
+    d, t = (_ci * 4)(*[int(v) for v in dims]), (_ci * 3)()
+    _check(lib().dwf_tune_tile_get(ctx.handle, d, int(tbc), t))
+    return tuple(t)
 
 
 def dwf_timing_enable(ctx, enable=True):

@@ -6,12 +6,16 @@ launch shape -- 4D sites per workgroup, s-slices per thread, XCD-aware workgroup
 or neighbour spinors staged in LDS -- keeps the fastest, installs it with ``dwf_tune_set`` and caches it in a JSON
 file keyed by (kernel, precision, Ls, lattice).  Shapes the kernel cannot run (more than 256
 threads, LDS above 64 KiB) are never tried: the library rejects them before launching.
+
+``tune_tile`` searches the traversal tile of a lattice the same way (``dwf_tune_tile``): the
+3D tile of spatial sites the workgroups walk along t, which sets how much of each input
+spinor's re-reads the L2 serves.
 """
 import json
 import os
 
 from . import (FP64, KIND_GAUGE, KIND_ODD, OP_MPREC, PREC_NAMES, DwfError, dwf_convert, dwf_dslash,
-               dwf_tune_get, dwf_tune_set)
+               dwf_tune_get, dwf_tune_set, dwf_tune_tile, dwf_tune_tile_get)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dwf_mi355x_tune.json")
 
@@ -58,20 +62,8 @@ def _time_mprec(lattice, Ug, src, dst, p, reps):
 
 def tune_hop(lattice, U64, prec, reps=5, cache=DEFAULT_CACHE, shapes=None, verbose=False):
     """Search the launch shapes for ``prec`` on ``lattice``; returns (best shape, ms, table)."""
-    import torch
     P = PREC_NAMES.get(prec, prec)
-    p = lattice.params(P)
-    Ug = U64
-    if P != FP64:
-        Ug = lattice.empty(KIND_GAUGE, P)
-        dwf_convert(lattice.ctx, lattice.params(P), KIND_GAUGE, FP64, U64, P, Ug)
-    tmp = lattice.zeros(KIND_ODD, FP64)
-    g = torch.Generator(device=tmp.device)
-    g.manual_seed(11)
-    tmp.view(torch.float64).normal_(generator=g)
-    src = lattice.empty(KIND_ODD, P)
-    dwf_convert(lattice.ctx, p, KIND_ODD, FP64, tmp, P, src)
-    dst = lattice.empty(KIND_ODD, P)
+    p, Ug, src, dst = _operands(lattice, U64, P)
     table = []
     best = None
     for c in shapes or candidates(P, lattice.Ls):
@@ -88,6 +80,58 @@ def tune_hop(lattice, U64, prec, reps=5, cache=DEFAULT_CACHE, shapes=None, verbo
     dwf_tune_set(lattice.ctx, P, lattice.Ls, best[0]["spb"], best[0]["ns"], best[0]["xcd"], best[0]["ll"])
     if cache:
         save(cache, _key(P, lattice.Ls, lattice.dims), dict(best[0], ms=best[1]))
+    return best[0], best[1], table
+
+
+def tile_candidates(dims, lo=64, hi=2048):
+    """3D traversal tiles whose extents divide the spatial extents, lo..hi sites per t-slice"""
+    def divs(L):
+        return [d for d in range(2, L + 1) if L % d == 0]
+    out = []
+    for tx in divs(dims[0]):
+        for ty in divs(dims[1]):
+            for tz in divs(dims[2]):
+                if lo <= tx * ty * tz <= hi:
+                    out.append((tx, ty, tz))
+    return out
+
+
+def _operands(lattice, U64, P):
+    import torch
+    p = lattice.params(P)
+    Ug = U64
+    if P != FP64:
+        Ug = lattice.empty(KIND_GAUGE, P)
+        dwf_convert(lattice.ctx, lattice.params(P), KIND_GAUGE, FP64, U64, P, Ug)
+    tmp = lattice.zeros(KIND_ODD, FP64)
+    g = torch.Generator(device=tmp.device)
+    g.manual_seed(11)
+    tmp.view(torch.float64).normal_(generator=g)
+    src = lattice.empty(KIND_ODD, P)
+    dwf_convert(lattice.ctx, p, KIND_ODD, FP64, tmp, P, src)
+    return p, Ug, src, lattice.empty(KIND_ODD, P)
+
+
+def tune_tile(lattice, U64, prec, tiles=None, reps=5, verbose=False):
+    """Search the traversal tile of the hop kernels for ``prec`` on ``lattice`` (timing M_prec
+    with the installed launch shape); installs the fastest and returns (tile, ms, table).  The
+    tile is a property of the lattice, shared by every precision and Ls on it."""
+    P = PREC_NAMES.get(prec, prec)
+    p, Ug, src, dst = _operands(lattice, U64, P)
+    default = dwf_tune_tile_get(lattice.ctx, lattice.dims, lattice.tbc)
+    table, best = [], None
+    for t in tiles or tile_candidates(lattice.dims):
+        try:
+            dwf_tune_tile(lattice.ctx, lattice.dims, t, lattice.tbc)
+        except DwfError:
+            continue
+        ms = _time_mprec(lattice, Ug, src, dst, p, reps)
+        table.append({"tile": list(t), "ms": ms, "default": tuple(t) == default})
+        if verbose:
+            print(f"tile {t}: {ms:.3f} ms", flush=True)
+        if best is None or ms < best[1]:
+            best = (tuple(t), ms)
+    dwf_tune_tile(lattice.ctx, lattice.dims, best[0], lattice.tbc)
     return best[0], best[1], table
 
 

@@ -56,14 +56,15 @@ __global__ void __launch_bounds__(256) hop_multi_kernel(const MultiGroup<P>* gro
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[0][k] = {R(0), R(0)};
     if (active) {
-      hop_dir<0, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<1, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<2, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<3, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<4, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<5, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<6, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
-      hop_dir<7, DAG, PRO, 1, false>(a, nb, L, s0, Ls, acc);
+      const ProCoef<R> pro[1] = {pro_coef<P, PRO>(a, s0)};
+      hop_dir<0, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<1, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<2, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<3, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<4, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<5, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<6, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
+      hop_dir<7, DAG, PRO, 1, false>(a, nb, L, s0, Ls, pro, acc);
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[0][k] = q.scale * acc[0][k];

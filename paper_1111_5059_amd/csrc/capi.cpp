@@ -466,6 +466,27 @@ int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* spb, int* n
   return DWF_OK;
 }
 
+int dwf_tune_tile(dwf_ctx* ctx, const int* dims, int tbc, const int* tile) {
+  if (!ctx || !dims || !tile) return fail(DWF_ERR_ARG, "NULL pointer");
+  for (int k = 0; k < 4; ++k)
+    if (dims[k] < 2 || dims[k] % 2) return fail(DWF_ERR_ARG, "lattice extents must be even and >= 2");
+  return guarded([&]() {
+    set_tile(ctx, dims, tbc, tile);
+    return DWF_OK;
+  });
+}
+
+int dwf_tune_tile_get(dwf_ctx* ctx, const int* dims, int tbc, int* tile) {
+  if (!ctx || !dims || !tile) return fail(DWF_ERR_ARG, "NULL pointer");
+  for (int k = 0; k < 4; ++k)
+    if (dims[k] < 2 || dims[k] % 2) return fail(DWF_ERR_ARG, "lattice extents must be even and >= 2");
+  return guarded([&]() {
+    const Geometry* g = geometry(ctx, dims, tbc);
+    for (int k = 0; k < 3; ++k) tile[k] = g->tile[k];
+    return DWF_OK;
+  });
+}
+
 int dwf_timing_enable(dwf_ctx* ctx, int enable) {
   if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
   return guarded([&]() {

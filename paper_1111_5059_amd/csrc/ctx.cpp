@@ -97,6 +97,76 @@ void timer_release(dwf_ctx* ctx) {
   t.used = 0;
 }
 
+// Default traversal tile: among the tiles whose extents divide the spatial extents and whose
+// t-slice holds at most 600 sites, the one with the smallest halo ratio
+// (tx+2)(ty+2)(tz+2) / (tx ty tz) -- the input sites one tile column reads per site it
+// writes -- ties going to the larger tz, then the larger tx.  A t-slice of a few hundred
+// sites keeps the three slices that share an input spinor within one XCD's L2 at FP64 too.
+void default_tile(const int dims[4], int tile[3]) {
+  double best = 1e300;
+  tile[0] = tile[1] = tile[2] = 1;
+  for (int tz = 1; tz <= dims[2]; ++tz) {
+    if (dims[2] % tz) continue;
+    for (int ty = 1; ty <= dims[1]; ++ty) {
+      if (dims[1] % ty) continue;
+      for (int tx = 1; tx <= dims[0]; ++tx) {
+        if (dims[0] % tx || long(tx) * ty * tz > 600) continue;
+        const double r = double(tx + 2) * (ty + 2) * (tz + 2) / (double(tx) * ty * tz);
+        const bool tie = r < best * (1 + 1e-12) && r > best * (1 - 1e-12);
+        if (r < best * (1 - 1e-12) || (tie && (tz > tile[2] || (tz == tile[2] && tx > tile[0])))) {
+          best = r;
+          tile[0] = tx;
+          tile[1] = ty;
+          tile[2] = tz;
+        }
+      }
+    }
+  }
+}
+
+// Tiled traversal order of the output sites: 3D tiles of (tx, ty, tz) sites walked along t,
+// tile after tile.  The 8 users of an input spinor are then processed within a few t-slices
+// of one tile (its halo also by the neighbouring tiles), a window that one XCD's L2 can hold.
+// Only the order in which workgroups visit sites changes; every result is the same.
+void upload_order(Geometry* g) {
+  const int X = g->dims[0], Y = g->dims[1], Z = g->dims[2], T = g->dims[3];
+  const int tx = g->tile[0], ty = g->tile[1], tz = g->tile[2];
+  const long ns = g->nsites;
+  auto idx = [&](int x, int y, int z, int t) { return long(x) + X * (long(y) + Y * (long(z) + long(Z) * t)); };
+  for (int p = 0; p < 2; ++p) {
+    std::vector<int> order;
+    order.reserve(ns);
+    for (int z0 = 0; z0 < Z; z0 += tz)
+      for (int y0 = 0; y0 < Y; y0 += ty)
+        for (int x0 = 0; x0 < X; x0 += tx)
+          for (int t = 0; t < T; ++t)
+            for (int z = z0; z < z0 + tz; ++z)
+              for (int y = y0; y < y0 + ty; ++y)
+                for (int x = x0; x < x0 + tx; ++x)
+                  if (((x + y + z + t) & 1) == p) order.push_back(int(idx(x, y, z, t) / 2));
+    if ((long)order.size() != ns) throw Error{DWF_ERR_ARG, "internal: traversal order incomplete"};
+    if (!g->d_order[p]) DWF_CHECK_HIP(hipMalloc(&g->d_order[p], ns * sizeof(int)));
+    DWF_CHECK_HIP(hipMemcpy(g->d_order[p], order.data(), ns * sizeof(int), hipMemcpyHostToDevice));
+  }
+}
+
+void set_tile(dwf_ctx* ctx, const int dims[4], int tbc, const int tile[3]) {
+  Geometry* g = const_cast<Geometry*>(geometry(ctx, dims, tbc));
+  int t[3];
+  if (tile[0] == 0 && tile[1] == 0 && tile[2] == 0) {
+    default_tile(dims, t);
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      if (tile[k] < 1 || dims[k] % tile[k] != 0) throw Error{DWF_ERR_ARG, "each tile extent must divide its lattice extent"};
+      t[k] = tile[k];
+    }
+  }
+  if (t[0] == g->tile[0] && t[1] == g->tile[1] && t[2] == g->tile[2]) return;
+  DWF_CHECK_HIP(hipStreamSynchronize(ctx->stream));  // no kernel may read the old order
+  for (int k = 0; k < 3; ++k) g->tile[k] = t[k];
+  upload_order(g);
+}
+
 // 4D checkerboard tables.  Lexicographic index i = x + X(y + Y(z + Z t)), parity
 // (x+y+z+t) mod 2, x_cb = i / 2 (X even).  For output parity p and site x_cb:
 // nbr = x_cb of x +- mu (in the other parity), linksrc = code of the link the hop
@@ -114,14 +184,7 @@ const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
   g->nsites = g->V / 2;
   if (4 * g->V * 2 >= (1L << 31)) throw Error{DWF_ERR_ARG, "lattice too large for 32-bit link codes"};
   const long ns = g->nsites;
-  // tile extents: the largest of 8, 6, 4, 2 dividing each spatial extent, shrunk until a
-  // t-slice of a tile holds at most 128 sites of one parity
-  auto pick = [](int L) { for (int c : {8, 6, 4, 2}) if (L % c == 0) return c; return L; };
-  g->tile[0] = pick(X); g->tile[1] = pick(Y); g->tile[2] = pick(Z);
-  for (int k = 2; g->tile[0] * g->tile[1] * g->tile[2] > 256 && k >= 0; --k) {
-    int& t = g->tile[k];
-    for (int c : {4, 2}) if (c < t && (k == 0 ? X : k == 1 ? Y : Z) % c == 0) { t = c; break; }
-  }
+  default_tile(dims, g->tile);
   std::vector<int> site(ns), nbr(ns * 8), lsrc(ns * 8);
   auto idx = [&](int x, int y, int z, int t) { return long(x) + X * (long(y) + Y * (long(z) + long(Z) * t)); };
   for (int p = 0; p < 2; ++p) {
@@ -151,23 +214,6 @@ const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
         lsrc[xc * 8 + 4 + mu] = int(2 * (long(mu) * g->V + jb) + phb);
       }
     }
-    // Tiled traversal order of the output sites: 3D tiles of (tx, ty, tz) sites walked
-    // along t, tile after tile.  All 8 users of an input spinor are then processed
-    // within a few t-slices of one tile, a window that stays in one XCD's L2.
-    std::vector<int> order;
-    order.reserve(ns);
-    const int tx = g->tile[0], ty = g->tile[1], tz = g->tile[2];
-    for (int z0 = 0; z0 < Z; z0 += tz)
-      for (int y0 = 0; y0 < Y; y0 += ty)
-        for (int x0 = 0; x0 < X; x0 += tx)
-          for (int t = 0; t < T; ++t)
-            for (int z = z0; z < z0 + tz; ++z)
-              for (int y = y0; y < y0 + ty; ++y)
-                for (int x = x0; x < x0 + tx; ++x)
-                  if (((x + y + z + t) & 1) == p) order.push_back(int(idx(x, y, z, t) / 2));
-    if ((long)order.size() != ns) throw Error{DWF_ERR_ARG, "internal: traversal order incomplete"};
-    DWF_CHECK_HIP(hipMalloc(&g->d_order[p], ns * sizeof(int)));
-    DWF_CHECK_HIP(hipMemcpy(g->d_order[p], order.data(), ns * sizeof(int), hipMemcpyHostToDevice));
     DWF_CHECK_HIP(hipMalloc(&g->d_site[p], ns * sizeof(int)));
     DWF_CHECK_HIP(hipMalloc(&g->d_nbr[p], ns * 8 * sizeof(int)));
     DWF_CHECK_HIP(hipMalloc(&g->d_linksrc[p], ns * 8 * sizeof(int)));
@@ -175,6 +221,7 @@ const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
     DWF_CHECK_HIP(hipMemcpy(g->d_nbr[p], nbr.data(), ns * 8 * sizeof(int), hipMemcpyHostToDevice));
     DWF_CHECK_HIP(hipMemcpy(g->d_linksrc[p], lsrc.data(), ns * 8 * sizeof(int), hipMemcpyHostToDevice));
   }
+  upload_order(g.get());
   ctx->geoms.push_back(std::move(g));
   return ctx->geoms.back().get();
 }

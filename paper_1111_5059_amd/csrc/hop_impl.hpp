@@ -47,24 +47,47 @@ inline size_t hop_lds_bytes(const LaunchCfg& cfg, int Ls, bool epi) {
   return b;
 }
 
+// Moebius prologue of one slice s: the hop's input becomes b_s psi_s + u P+ psi_{s-1} +
+// l P- psi_{s+1} (F = b + c S~ with the -m wrap at the ends of the fifth dimension).  The
+// coefficients depend on s only; they are formed once per thread, before the direction loop,
+// so that the eight directions form one straight-line block the scheduler can interleave
+// (selected per direction, they split it into small blocks and the loads of all directions
+// were issued before any arithmetic, which spilled).
+template <typename R>
+struct ProCoef {
+  R b, u, l;
+  int su, sl;
+};
+
 template <typename P, bool PRO>
-__device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, cx<typename P::R> psi[12]) {
+__device__ __forceinline__ ProCoef<typename P::R> pro_coef(const HopArgs<P>& a, int s) {
+  using R = typename P::R;
+  ProCoef<R> c{R(0), R(0), R(0), 0, 0};
+  if constexpr (PRO) {
+    const int Ls = a.Ls;
+    const R pb = a.pbs ? a.pbs[s] : a.pb, pc = a.pcs ? a.pcs[s] : a.pc;  // coefficients of slice s
+    c.b = pb;
+    c.su = s == 0 ? Ls - 1 : s - 1;
+    c.sl = s == Ls - 1 ? 0 : s + 1;
+    c.u = s == 0 ? -pc * a.pm : pc;
+    c.l = s == Ls - 1 ? -pc * a.pm : pc;
+  }
+  return c;
+}
+
+template <typename P, bool PRO>
+__device__ __forceinline__ void load_input(const HopArgs<P>& a, long y, int s, const ProCoef<typename P::R>& pc,
+                                           cx<typename P::R> psi[12]) {
   using R = typename P::R;
   load_spinor<P>(a.in, y, s, a.Ls, psi);
   if constexpr (PRO) {
-    const int Ls = a.Ls;
     cx<R> up[6], lo[6];
-    int su = s - 1, sl = s + 1;
-    const R pb = a.pbs ? a.pbs[s] : a.pb, pc = a.pcs ? a.pcs[s] : a.pc;  // coefficients of slice s
-    R fu = pc, fl = pc;
-    if (su < 0) { su = Ls - 1; fu = -pc * a.pm; }
-    if (sl >= Ls) { sl = 0; fl = -pc * a.pm; }
-    load_half_spinor<P>(a.in, y, su, Ls, 0, up);  // P+ (spins 0,1) picks psi_{s-1}
-    load_half_spinor<P>(a.in, y, sl, Ls, 6, lo);  // P- (spins 2,3) picks psi_{s+1}
+    load_half_spinor<P>(a.in, y, pc.su, a.Ls, 0, up);  // P+ (spins 0,1) picks psi_{s-1}
+    load_half_spinor<P>(a.in, y, pc.sl, a.Ls, 6, lo);  // P- (spins 2,3) picks psi_{s+1}
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      psi[k] = pb * psi[k] + fu * up[k];
-      psi[6 + k] = pb * psi[6 + k] + fl * lo[k];
+      psi[k] = pc.b * psi[k] + pc.u * up[k];
+      psi[6 + k] = pc.b * psi[6 + k] + pc.l * lo[k];
     }
   }
 }
@@ -169,16 +192,12 @@ __device__ __forceinline__ void links_f16(const __half2* L, int D, f16x2 Uc[9], 
 // terms (psi_s, the upper spins of psi_{s-1}, the lower spins of psi_{s+1}, each with its own
 // norm) are weighted relative to the largest weight, so every packed value stays within the
 // FP16 range (|value| <= 2); the largest weight is returned as the norm of the result.
-__device__ __forceinline__ float load_input_f16_pro(const HopArgs<P16>& a, long y, int s, f16x2 psi[12]) {
-  const int Ls = a.Ls;
+__device__ __forceinline__ float load_input_f16_pro(const HopArgs<P16>& a, long y, int s, const ProCoef<float>& pc,
+                                                  f16x2 psi[12]) {
+  const int Ls = a.Ls, su = pc.su, sl = pc.sl;
   const __half2* p = a.in.data + size_t(y) * 12 * Ls;
   const float* nb = a.in.norm + size_t(y) * Ls;
-  int su = s - 1, sl = s + 1;
-  const float pb = a.pbs ? a.pbs[s] : a.pb, pc = a.pcs ? a.pcs[s] : a.pc;  // coefficients of slice s
-  float fu = pc, fl = pc;
-  if (su < 0) { su = Ls - 1; fu = -pc * a.pm; }
-  if (sl >= Ls) { sl = 0; fl = -pc * a.pm; }
-  const float ws = pb * nb[s], wu = fu * nb[su], wl = fl * nb[sl];
+  const float ws = pc.b * nb[s], wu = pc.u * nb[su], wl = pc.l * nb[sl];
   const float m = fmaxf(fabsf(ws), fmaxf(fabsf(wu), fabsf(wl)));
   const float inv = m > 1e-37f ? __builtin_amdgcn_rcpf(m) : 0.0f;  // (ratios only need FP16 accuracy)
   const _Float16 hs = (_Float16)(ws * inv), hu = (_Float16)(wu * inv), hl = (_Float16)(wl * inv);
@@ -192,7 +211,7 @@ __device__ __forceinline__ float load_input_f16_pro(const HopArgs<P16>& a, long 
 
 template <int MU, int SG, int NS, bool PRO, bool PAIRED>
 __device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const __half2* L, int D, int s0, int tps,
-                                            cx<float> (&acc)[NS][12]) {
+                                            const ProCoef<float> (&pro)[NS], cx<float> (&acc)[NS][12]) {
   f16x2 Uc[9], Us[9];
   links_f16<PAIRED>(L, D, Uc, Us);
   const int Ls = a.Ls;
@@ -202,7 +221,7 @@ __device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const
     f16x2 psi[12], h[6];
     float n;
     if constexpr (PRO) {
-      n = load_input_f16_pro(a, y, s, psi);
+      n = load_input_f16_pro(a, y, s, pro[j], psi);
     } else {
       const __half2* p = a.in.data + size_t(y) * 12 * Ls + s;
 #pragma unroll
@@ -309,14 +328,14 @@ __device__ __forceinline__ void staged_step(const HopArgs<P16>& a, const int* ys
 // PAIRED: FP16 links staged as (U, Us) pairs, 20 elements per direction.
 template <int D, bool DAG, bool PRO, int NS, bool PAIRED, typename P>
 __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, const typename P::S* L, int s0, int tps,
-                                        cx<typename P::R> (&acc)[NS][12]) {
+                                        const ProCoef<typename P::R> (&pro)[NS], cx<typename P::R> (&acc)[NS][12]) {
   using R = typename P::R;
   constexpr int MU = D & 3;
   constexpr bool FWD = D < 4;
   constexpr int SG = (FWD != DAG) ? -1 : +1;
   const long y = nb[D];
   if constexpr (std::is_same<P, P16>::value) {
-    hop_dir_f16<MU, SG, NS, PRO, PAIRED>(a, y, L, D, s0, tps, acc);
+    hop_dir_f16<MU, SG, NS, PRO, PAIRED>(a, y, L, D, s0, tps, pro, acc);
     return;
   }
   constexpr int LSTR = PAIRED ? 20 : 9, LEL = PAIRED ? 2 : 1;
@@ -326,7 +345,7 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, cons
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     cx<R> psi[12], h[6], u[6];
-    load_input<P, PRO>(a, y, s0 + j * tps, psi);
+    load_input<P, PRO>(a, y, s0 + j * tps, pro[j], psi);
     project<MU, SG>(psi, h);
     su3_mul_half(U, h, u);
     reconstruct_acc<MU, SG>(u, acc[j]);
@@ -334,15 +353,16 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, cons
 }
 
 // FP16: at least 5 waves per SIMD (at most 102 VGPRs), since the kernel is bound by memory
-// latency; not with the fused CG step, whose extra operands would then spill
-template <typename P, bool CG>
-constexpr int hop_min_waves() { return std::is_same<P, P16>::value && !CG ? 5 : 1; }
+// latency; not with the fused CG step or several slices per thread, whose extra operands
+// would then spill
+template <typename P, int NS, bool CG>
+constexpr int hop_min_waves() { return std::is_same<P, P16>::value && NS == 1 && !CG ? 5 : 1; }
 
 // ST: neighbour spinors staged through LDS (FP16, compile-time Ls, one slice per lane, no
 // prologue, spb = 256 / Ls); its links are staged too (LL), so that the direction loop issues
 // no other vector-memory loads than the copies
 template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST>
-__global__ void __launch_bounds__(256, (hop_min_waves<P, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
+__global__ void __launch_bounds__(256, (hop_min_waves<P, NS, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
@@ -417,14 +437,17 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, CG>())) hop_kernel(HopA
     staged_step<7, DAG, LS>(ak, ys, spb, nact, active, lsite, s0, L, sbuf, acc);
   } else if (active) {
     const int* nb = a.nbr + x * 8;
-    hop_dir<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<1, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<2, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<3, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<4, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<5, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<6, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
-    hop_dir<7, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, acc);
+    ProCoef<R> pro[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) pro[j] = pro_coef<P, PRO>(ak, s0 + j * tps);
+    hop_dir<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<1, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<2, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<3, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<4, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<5, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<6, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    hop_dir<7, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
   }
   if constexpr (!std::is_same<P, P16>::value) {  // (the FP16 path folds the scale into the norm)
 #pragma unroll

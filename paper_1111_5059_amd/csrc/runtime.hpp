@@ -99,6 +99,8 @@ namespace dwf {
 
 void* ws_get(dwf_ctx* ctx, const std::string& name, size_t bytes);
 const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc);
+// traversal tile of the hop kernels on one lattice (0, 0, 0: the default)
+void set_tile(dwf_ctx* ctx, const int dims[4], int tbc, const int tile[3]);
 LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls);
 // device buffer of the fifth-dimension matrices for one parameter set
 // (bs, cs: optional s-dependent Moebius coefficients, Ls entries each)

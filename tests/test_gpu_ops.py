@@ -258,3 +258,47 @@ def test_autotuner_installs_the_fastest_shape(env, tmp_path):
         assert autotune.current(lat, "fp32") == best
     finally:
         dwf.dwf_tune_set(ctx, dwf.FP32, Ls, 0, 0)
+
+
+def test_traversal_tile_changes_nothing_but_the_order(env, ora):
+    """Every traversal tile gives bit-identical M_prec and M_prec^dag (the tile only reorders
+    the workgroups' sites) that agree with the oracle; tiles that do not divide the lattice
+    are rejected; (0, 0, 0) restores the default; the tile search installs its fastest tile."""
+    from paper_1111_5059_amd import autotune
+    dwf, ctx = env
+    P = dwf.FP32
+    dims, Ls = (12, 4, 6, 8), 8
+    U, psi = make(dims, Ls, 840)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.05, b=1.5, c=0.5, tbc=1)
+    Ug = lat.pack_gauge(U, P)
+    po = ora.params(dims, Ls, mass=0.05, b=1.5, c=0.5, tbc=1)
+    psio = mask(psi, dims, 1)
+    src = lat.pack(psio, dwf.KIND_ODD, P)
+    default = dwf.dwf_tune_tile_get(ctx, dims, 1)
+    assert all(dims[k] % default[k] == 0 for k in range(3))
+
+    def apply(dag):
+        dst = lat.empty(dwf.KIND_ODD, P)
+        dwf.mobius_dslash(ctx, lat.params(P), Ug, src, dst, dwf.OP_MPREC, 1, dag)
+        return lat.unpack_np(dst, dwf.KIND_ODD, P)
+
+    first = {dag: apply(dag) for dag in (False, True)}
+    for dag in (False, True):
+        assert rel_err(first[dag], ora.mprec(po, U, psio, dagger=dag)) < PREC_TOL["fp32"]
+    try:
+        for tile in [(2, 2, 2), (12, 4, 6), (4, 2, 3), (6, 4, 2), (3, 1, 1)]:
+            dwf.dwf_tune_tile(ctx, dims, tile, 1)
+            assert dwf.dwf_tune_tile_get(ctx, dims, 1) == tile
+            for dag in (False, True):
+                assert np.array_equal(apply(dag), first[dag]), (tile, dag)
+        for bad in [(5, 4, 6), (12, 4, 0), (24, 4, 6), (-2, 4, 6)]:
+            with pytest.raises(dwf.DwfError):
+                dwf.dwf_tune_tile(ctx, dims, bad, 1)
+        best, ms, table = autotune.tune_tile(lat, lat.pack_gauge(U), "fp32", tiles=[(2, 2, 2), (6, 4, 6)], reps=2)
+        assert len(table) == 2 and ms == min(r["ms"] for r in table)
+        assert dwf.dwf_tune_tile_get(ctx, dims, 1) == best
+    finally:
+        dwf.dwf_tune_tile(ctx, dims, (0, 0, 0), 1)
+    assert dwf.dwf_tune_tile_get(ctx, dims, 1) == default
+    for dag in (False, True):
+        assert np.array_equal(apply(dag), first[dag])
