@@ -426,7 +426,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"f32 arithmetic ({args.inner} inner / fp32 PV and final storage), f64 residuals and accumulator",
+        "dtype": f"f32 arithmetic ({args.inner} inner / {args.pv_prec} PV / {args.final_prec} final storage), "
+                 "f64 residuals and accumulator",
         "data": "synthetic",
         "config": {"workload": desc, "dims": list(dims), "Ls": L, "Ls_inner": Lp, "mass": mass, "eps": eps,
                    "n_dc": args.n_dc, "tol": 1e-10, "tol_mobius": args.tol_mobius, "tol_pv": args.tol_pv,
