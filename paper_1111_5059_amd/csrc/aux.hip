@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(RED_THREADS) dot_kernel(CHalf<P> a, CHalf<P> b
 // One workgroup of 1024 threads; each thread keeps four independent partial sums (loads in
 // flight) over a fixed set of indices, combined in a fixed order: deterministic.
 __global__ void __launch_bounds__(1024) reduce_kernel(const double* partials, int n, int ncomp, double* scalars,
-                                                       int slot, int mode) {
+                                                       int slot, int mode, int hist) {
   __shared__ double red[16];
   for (int c = 0; c < ncomp; ++c) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -86,6 +86,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(const double* partials, in
       if (mode == 1) {
         // alpha = rr / qq
         scalars[S_ALPHA] = scalars[S_RR] / t;
+        if (hist >= 0) scalars[S_AHIST + hist] = scalars[S_ALPHA];
       } else if (mode == 2) {
         // beta = rr_new / rr ; rr = rr_new
         scalars[S_BETA] = t / scalars[S_RR];
@@ -95,8 +96,10 @@ __global__ void __launch_bounds__(1024) reduce_kernel(const double* partials, in
   }
 }
 
-int launch_reduce(const double* partials, int n, int ncomp, double* scalars, int slot, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, partials, n, ncomp, scalars, slot, mode);
+int launch_reduce(const double* partials, int n, int ncomp, double* scalars, int slot, int mode, hipStream_t st,
+                  int hist) {
+  if (hist >= XFLUSH_MAX) return -1;
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, partials, n, ncomp, scalars, slot, mode, hist);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -217,8 +220,8 @@ int launch_cg_update(Half<Px> x, CHalf<P> p, Half<P> r, CHalf<P> Ap, const doubl
 
 // p = r + beta p ; the first thread also records rr_new as the current |r|^2 (S_RR)
 template <typename P>
-__global__ void __launch_bounds__(256) cg_pupdate_kernel(CHalf<P> r, Half<P> p, double beta, double* scalars,
-                                                          double rr_new, long n5, int Ls) {
+__global__ void __launch_bounds__(256) cg_pupdate_kernel(CHalf<P> r, CHalf<P> pin, Half<P> pout, double beta,
+                                                          double* scalars, double rr_new, long n5, int Ls) {
   using R = typename P::R;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) scalars[S_RR] = rr_new;
@@ -228,7 +231,7 @@ __global__ void __launch_bounds__(256) cg_pupdate_kernel(CHalf<P> r, Half<P> p, 
   cx<R> rv[12], pv[12];
   load_spinor<P>(r, xs, s, Ls, rv);
   if (beta != 0.0) {
-    load_spinor<P>(CHalf<P>{p.data, p.norm}, xs, s, Ls, pv);
+    load_spinor<P>(pin, xs, s, Ls, pv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       pv[k].re = R(double(rv[k].re) + beta * double(pv[k].re));
@@ -238,15 +241,56 @@ __global__ void __launch_bounds__(256) cg_pupdate_kernel(CHalf<P> r, Half<P> p, 
 #pragma unroll
     for (int k = 0; k < 12; ++k) pv[k] = rv[k];
   }
-  store_spinor<P>(p, xs, s, Ls, pv);
+  store_spinor<P>(pout, xs, s, Ls, pv);
 }
 
 template <typename P>
-int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, double rr_new, long n5, int Ls,
-                      hipStream_t st) {
+int launch_cg_pupdate(CHalf<P> r, CHalf<P> pin, Half<P> pout, double beta, double* scalars, double rr_new, long n5,
+                      int Ls, hipStream_t st) {
   if (n5 <= 0) return 0;
-  hipLaunchKernelGGL((cg_pupdate_kernel<P>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, r, p, beta,
-                     scalars, rr_new, n5, Ls);
+  hipLaunchKernelGGL((cg_pupdate_kernel<P>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, r, pin, pout,
+                     beta, scalars, rr_new, n5, Ls);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// x += sum_j alpha_j p_j over the pending CG directions (alpha_j = scalars[S_AHIST + slot_j]):
+// the solution increment of several iterations in one pass, the sum formed in FP64
+template <typename P, typename Px>
+__global__ void __launch_bounds__(256) xflush_kernel(Half<Px> x, XFlush<P> f, const double* scalars, long n5,
+                                                      int Ls) {
+  using RX = typename Px::R;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n5) return;
+  const long xs = i / Ls;
+  const int s = int(i - xs * Ls);
+  double sr[12], si[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) sr[k] = si[k] = 0.0;
+  for (int j = 0; j < f.n; ++j) {
+    const double a = scalars[S_AHIST + f.slot[j]];
+    cx<typename P::R> pv[12];
+    load_spinor<P>(f.p[j], xs, s, Ls, pv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      sr[k] += a * double(pv[k].re);
+      si[k] += a * double(pv[k].im);
+    }
+  }
+  cx<RX> xv[12];
+  load_spinor<Px>(CHalf<Px>{x.data, x.norm}, xs, s, Ls, xv);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) xv[k] = {RX(double(xv[k].re) + sr[k]), RX(double(xv[k].im) + si[k])};
+  store_spinor<Px>(x, xs, s, Ls, xv);
+}
+
+template <typename P, typename Px>
+int launch_xflush(Half<Px> x, const XFlush<P>& f, const double* scalars, long n5, int Ls, hipStream_t st) {
+  if (f.n < 0 || f.n > XFLUSH_MAX) return -1;
+  for (int j = 0; j < f.n; ++j)
+    if (f.slot[j] < 0 || f.slot[j] >= XFLUSH_MAX || !f.p[j].data) return -1;
+  if (n5 <= 0 || f.n == 0) return 0;
+  hipLaunchKernelGGL((xflush_kernel<P, Px>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, x, f, scalars, n5,
+                     Ls);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -492,7 +536,7 @@ int launch_convert_links(const typename Pi::S* in, typename Po::S* out, long n, 
   template int launch_norm2<P>(CHalf<P>, long, int, double*, hipStream_t);                                       \
   template int launch_dot<P>(CHalf<P>, CHalf<P>, long, int, double*, hipStream_t);                               \
   template int launch_axpby<P>(double, CHalf<P>, double, Half<P>, long, int, hipStream_t);                        \
-  template int launch_cg_pupdate<P>(CHalf<P>, Half<P>, double, double*, double, long, int, hipStream_t);        \
+  template int launch_cg_pupdate<P>(CHalf<P>, CHalf<P>, Half<P>, double, double*, double, long, int, hipStream_t); \
   template int launch_cg_pupdate_f<P>(CHalf<P>, CHalf<P>, Half<P>, Half<P>, double, double*, double, long, int,   \
                                       double, double, double, hipStream_t, const P::R*, const P::R*);           \
   template int launch_pack_gauge<P>(const GeomTables&, const double2*, P::S*, hipStream_t);                      \
@@ -516,6 +560,11 @@ template int launch_convert<P32, P16>(CHalf<P32>, Half<P16>, long, int, hipStrea
 template int launch_convert<P16, P32>(CHalf<P16>, Half<P32>, long, int, hipStream_t);
 template int launch_convert<P32, PB16>(CHalf<P32>, Half<PB16>, long, int, hipStream_t);
 template int launch_convert<PB16, P32>(CHalf<PB16>, Half<P32>, long, int, hipStream_t);
+
+template int launch_xflush<P64, P64>(Half<P64>, const XFlush<P64>&, const double*, long, int, hipStream_t);
+template int launch_xflush<P32, P32>(Half<P32>, const XFlush<P32>&, const double*, long, int, hipStream_t);
+template int launch_xflush<P16, P32>(Half<P32>, const XFlush<P16>&, const double*, long, int, hipStream_t);
+template int launch_xflush<PB16, P32>(Half<P32>, const XFlush<PB16>&, const double*, long, int, hipStream_t);
 
 template int launch_cg_update<P64, P64>(Half<P64>, CHalf<P64>, Half<P64>, CHalf<P64>, const double*, long, int,
                                         double*, hipStream_t);

@@ -512,20 +512,11 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, NS, CG>())) hop_kernel(
         for (int k = 0; k < 12; ++k) acc[j][k] = acc[j][k] + a.ax * xv[k];
       }
       if constexpr (CG) {
-        // r -= alpha v, xl += alpha p: the CG vector updates on the site this thread holds
-        using PX = typename IncrementPrec<P>::type;
-        using RX = typename PX::R;
-        cx<R> rv[12], pv[12];
-        cx<RX> xl[12];
+        // r -= alpha v: the CG residual update on the site this thread holds
+        cx<R> rv[12];
         load_spinor<P>(CHalf<P>{a.cg_r.data, a.cg_r.norm}, x, s, Ls, rv);
-        load_spinor<P>(a.cg_p, x, s, Ls, pv);
-        load_spinor<PX>(CHalf<PX>{a.cg_x.data, a.cg_x.norm}, x, s, Ls, xl);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          rv[k] = {rv[k].re - alpha * acc[j][k].re, rv[k].im - alpha * acc[j][k].im};
-          xl[k] = {xl[k].re + RX(alpha) * RX(pv[k].re), xl[k].im + RX(alpha) * RX(pv[k].im)};
-        }
-        store_spinor<PX>(a.cg_x, x, s, Ls, xl);
+        for (int k = 0; k < 12; ++k) rv[k] = {rv[k].re - alpha * acc[j][k].re, rv[k].im - alpha * acc[j][k].im};
         store_spinor<P>(a.cg_r, x, s, Ls, rv);
         if (a.norm_partials) {
 #pragma unroll
@@ -630,7 +621,7 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
   if (cfg.ns != 1 && cfg.ns != 2 && cfg.ns != 4) return -1;
   if (a.Ls % cfg.ns != 0 || cfg.spb < 1) return -1;
   if (dagger && prologue) return -1;
-  if (a.cg_r.data && (!dagger || !a.cg_p.data || !a.cg_x.data || !a.cg_scalars)) return -1;
+  if (a.cg_r.data && (!dagger || !a.cg_scalars)) return -1;
   const int threads = cfg.spb * (a.Ls / cfg.ns);
   if (threads > 256) return -1;
   if (hop_lds_bytes<P>(cfg, a.Ls, a.E != nullptr) > 65536) return -1;

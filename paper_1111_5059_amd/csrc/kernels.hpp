@@ -49,10 +49,10 @@ struct HopArgs {
   Half<P> out2 = {nullptr, nullptr};
   FifthScan<typename P::R> es2;
   // CG step fused into the last hop of M^dag M p (cg_r.data == nullptr: none).  With it the
-  // result v is not stored; instead r -= alpha v and xl += alpha p, alpha = cg_scalars[S_ALPHA].
+  // result v is not stored; instead r -= alpha v, alpha = cg_scalars[S_ALPHA], and the
+  // partials are those of the new |r|^2 (the solution increment is summed separately, a few
+  // iterations at a time).
   Half<P> cg_r = {nullptr, nullptr};
-  CHalf<P> cg_p = {nullptr, nullptr};
-  Half<typename IncrementPrec<P>::type> cg_x = {nullptr, nullptr};  // solution increment
   const double* cg_scalars = nullptr;
 };
 
@@ -91,18 +91,31 @@ int launch_axpby(double a, CHalf<P> x, double b, Half<P> y, long n5, int Ls, hip
 template <typename Pi, typename Po>
 int launch_convert(CHalf<Pi> in, Half<Po> out, long n5, int Ls, hipStream_t st);
 // scalar slots on the device (CG scalars)
-enum ScalarSlot { S_RR = 0, S_RRNEW, S_QQ, S_ALPHA, S_BETA, S_TMP0, S_TMP1, S_TMP2, S_COUNT = 16 };
+// S_AHIST .. S_AHIST + XFLUSH_MAX - 1: alpha of the iterations whose increments are pending
+enum ScalarSlot { S_RR = 0, S_RRNEW, S_QQ, S_ALPHA, S_BETA, S_TMP0, S_TMP1, S_TMP2, S_AHIST = 8, S_COUNT = 16 };
+constexpr int XFLUSH_MAX = S_COUNT - S_AHIST;
 // dst[slot] = sum(partials[0..n)) and the CG scalar update selected by mode:
-//   0: just store;  1: alpha = rr/qq (slot = S_QQ);  2: beta = rrnew/rr, rr = rrnew (slot = S_RRNEW)
-int launch_reduce(const double* partials, int n, int ncomp, double* scalars, int slot, int mode, hipStream_t st);
+//   0: just store;  1: alpha = rr/qq (slot = S_QQ), also stored at S_AHIST + hist when hist >= 0;
+//   2: beta = rrnew/rr, rr = rrnew (slot = S_RRNEW)
+int launch_reduce(const double* partials, int n, int ncomp, double* scalars, int slot, int mode, hipStream_t st,
+                  int hist = -1);
+// pending CG directions: x += sum_j scalars[S_AHIST + slot[j]] p[j], j < n
+template <typename P>
+struct XFlush {
+  CHalf<P> p[XFLUSH_MAX];
+  int slot[XFLUSH_MAX];
+  int n = 0;
+};
+template <typename P, typename Px>
+int launch_xflush(Half<Px> x, const XFlush<P>& f, const double* scalars, long n5, int Ls, hipStream_t st);
 // x += alpha p  (x in Px, p in P);  r -= alpha Ap;  partials of |r|^2
 template <typename P, typename Px>
 int launch_cg_update(Half<Px> x, CHalf<P> p, Half<P> r, CHalf<P> Ap, const double* scalars, long n5, int Ls,
                      double* partials, hipStream_t st);
-// p = r + beta p  (and scalars[S_RR] = rr_new)
+// p_out = r + beta p_in (p_in unused when beta = 0; it may be p_out) and scalars[S_RR] = rr_new
 template <typename P>
-int launch_cg_pupdate(CHalf<P> r, Half<P> p, double beta, double* scalars, double rr_new, long n5, int Ls,
-                      hipStream_t st);
+int launch_cg_pupdate(CHalf<P> r, CHalf<P> pin, Half<P> pout, double beta, double* scalars, double rr_new, long n5,
+                      int Ls, hipStream_t st);
 // p_out = r + beta p_in (p_in unused when beta = 0) and fp = (b + c S~) p_out, rr_new -> S_RR
 template <typename P>
 int launch_cg_pupdate_f(CHalf<P> r, CHalf<P> pin, Half<P> pout, Half<P> fp, double beta, double* scalars,

@@ -191,8 +191,6 @@ struct Op {
   // CG step fused into a dagger hop (r.data == nullptr: none)
   struct CgStep {
     Half<P> r = {nullptr, nullptr};
-    CHalf<P> p = {nullptr, nullptr};
-    Half<typename IncrementPrec<P>::type> x = {nullptr, nullptr};
     const double* scalars = nullptr;
   };
 
@@ -204,8 +202,6 @@ struct Op {
     a.out2 = out2;
     if (out2.data) a.es2 = es[slot2];
     a.cg_r = cg.r;
-    a.cg_p = cg.p;
-    a.cg_x = cg.x;
     a.cg_scalars = cg.scalars;
     a.in = in;
     a.out = out;
@@ -235,11 +231,9 @@ struct Op {
     if (ctx->timer.on) mark = timer_begin(ctx, hop_name(a, dag, pro && moebius));
     DWF_CHECK_LAUNCH(launch_hop<P>(a, dag, pro && moebius, cfg, ctx->stream));
     if (mark >= 0) {
-      // fields read and written once: in, out (or with the CG step: r, p read, r written, the
-      // increment xl read and written), x
+      // fields read and written once: in, out (or with the CG step: r read and written), x
       const double fb = spinor_site_bytes<P>();
-      const double bytes = cg.r.data ? fb * (4 + (x.data ? 1 : 0)) + 2 * spinor_site_bytes<typename IncrementPrec<P>::type>()
-                                     : fb * (2 + (x.data ? 1 : 0) + (out2.data ? 1 : 0));
+      const double bytes = cg.r.data ? fb * (3 + (x.data ? 1 : 0)) : fb * (2 + (x.data ? 1 : 0) + (out2.data ? 1 : 0));
       timer_end(ctx, mark, double(n5()) * bytes + double(g->nsites) * 72 * sizeof(S));
     }
   }
@@ -288,18 +282,15 @@ struct Op {
     hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
     hop(1, cv(tmp_e), out, true, false, -0.25, moebius ? em(E_FDAG) : nullptr, in, 1.0, partials);
   }
-  // M_prec^dag q with the CG step fused into its last hop: r -= alpha M_prec^dag q,
-  // xl += alpha p, per-workgroup partials of |r|^2 (alpha read from scalars on the device)
+  // M_prec^dag q with the CG step fused into its last hop: r -= alpha M_prec^dag q and the
+  // per-workgroup partials of |r|^2 (alpha read from scalars on the device)
   // (ainvdag_ready: tmp_o already holds A^-dag in, the second output of mprec)
-  void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, CHalf<P> p,
-                    Half<typename IncrementPrec<P>::type> xl, const double* scalars, double* partials,
+  void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, const double* scalars, double* partials,
                     bool ainvdag_ready = false) const {
     if (!ainvdag_ready) fifth(in, tmp_o, E_AINVDAG);
     hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
     CgStep cg;
     cg.r = r;
-    cg.p = p;
-    cg.x = xl;
     cg.scalars = scalars;
     hop(1, cv(tmp_e), Half<P>{nullptr, nullptr}, true, false, -0.25, moebius ? em(E_FDAG) : nullptr, in, 1.0, partials,
         cg);

@@ -97,7 +97,6 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   // inner vectors
   Half<Pi> r = hview<Pi>(MIXED ? ws_get(ctx, tag + ".r." + pname(Pi::ID), hbi) : (void*)rhi.data, g, Ls);
   if (!MIXED) r = hview<Pi>((void*)rhi.data, g, Ls);
-  Half<Pi> p = hview<Pi>(ws_get(ctx, tag + ".p." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> q = hview<Pi>(ws_get(ctx, tag + ".q." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> te = hview<Pi>(ws_get(ctx, tag + ".te." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> to = hview<Pi>(ws_get(ctx, tag + ".to." + pname(Pi::ID), hbi), g, Ls);
@@ -106,19 +105,36 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
     DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
     DWF_CHECK_LAUNCH(launch_zero(xl.data, half_size<PX>(g, Ls), s));
   }
-  // Moebius operators: the p update also forms F p (two p buffers), and M p runs without
-  // the input factor in its hops
+  // The search directions rotate through a ring of KX buffers and the solution increment
+  // xl += alpha_k p_k is applied KX iterations at a time (one pass that reads the KX
+  // directions and xl once, instead of xl read and written in every iteration), and before
+  // every reliable update and at the end.  The alphas wait in the scalar history slots.
+  constexpr int KX = 4;
+  static_assert(KX >= 2 && KX <= XFLUSH_MAX, "direction ring");
+  Half<Pi> pr[KX];
+  for (int j = 0; j < KX; ++j) pr[j] = hview<Pi>(ws_get(ctx, tag + ".p" + std::to_string(j) + "." + pname(Pi::ID), hbi), g, Ls);
+  int cur = 0;  // ring index of the current direction
+  XFlush<Pi> pend;
+  auto flush = [&]() {
+    DWF_CHECK_LAUNCH((launch_xflush<Pi, PX>(xl, pend, sc, n5, Ls, s)));
+    pend.n = 0;
+  };
+  // Moebius operators: the p update also forms F p, and M p runs without the input factor in
+  // its hops
   const bool PRE = opi.moebius;
-  Half<Pi> p2 = PRE ? hview<Pi>(ws_get(ctx, tag + ".p2." + pname(Pi::ID), hbi), g, Ls) : Half<Pi>{nullptr, nullptr};
   Half<Pi> fp = PRE ? hview<Pi>(ws_get(ctx, tag + ".fp." + pname(Pi::ID), hbi), g, Ls) : Half<Pi>{nullptr, nullptr};
+  // the new direction goes to the next ring slot: never a pending one, since at most KX - 1
+  // are pending here, the last of them the current one
   auto p_update = [&](double beta, double rr_new) {
+    const int nxt = (cur + 1) % KX;
     if (PRE) {
-      DWF_CHECK_LAUNCH(launch_cg_pupdate_f<Pi>(cv(r), cv(p), p2, fp, beta, sc, rr_new, n5, Ls, opi.b, opi.c, opi.m, s,
-                                               opi.sdep ? opi.coef_b : nullptr, opi.sdep ? opi.coef_c : nullptr));
-      std::swap(p, p2);
+      DWF_CHECK_LAUNCH(launch_cg_pupdate_f<Pi>(cv(r), cv(pr[cur]), pr[nxt], fp, beta, sc, rr_new, n5, Ls, opi.b, opi.c,
+                                               opi.m, s, opi.sdep ? opi.coef_b : nullptr,
+                                               opi.sdep ? opi.coef_c : nullptr));
     } else {
-      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), p, beta, sc, rr_new, n5, Ls, s));
+      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(r), cv(pr[cur]), pr[nxt], beta, sc, rr_new, n5, Ls, s));
     }
+    cur = nxt;
   };
   // p = r
   p_update(0.0, rr);
@@ -127,15 +143,20 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
   int it = 0;
   while (it < maxit) {
-    // q = M p, |q|^2 -> alpha = rr / |q|^2
+    const Half<Pi> p = pr[cur];
+    // q = M p, |q|^2 -> alpha = rr / |q|^2 (also kept in the history slot of this direction)
     // (with A^-dag q, the first step of M^dag q, as a second output of the last hop)
     const Half<Pi> q2 = OUT2 ? to : Half<Pi>{nullptr, nullptr};
     if (PRE) opi.mprec_pre(cv(fp), cv(p), q, te, part, q2);
     else opi.mprec(cv(p), q, te, part, q2);
-    DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_QQ, 1, s));
-    // r -= alpha M^dag q, xl += alpha p, |r|^2, fused into the last hop of M^dag q
-    opi.mprec_dag_cg(cv(q), to, te, r, cv(p), xl, sc, part, OUT2);
+    DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_QQ, 1, s, pend.n));
+    pend.p[pend.n] = cv(p);
+    pend.slot[pend.n] = pend.n;
+    ++pend.n;
+    // r -= alpha M^dag q and |r|^2, fused into the last hop of M^dag q
+    opi.mprec_dag_cg(cv(q), to, te, r, sc, part, OUT2);
     DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_RRNEW, 0, s));
+    if (pend.n == KX) flush();
     double rr_new = read_scalar(ctx, sc, S_RRNEW);
     ++it;
     if (!std::isfinite(rr_new)) throw Error{DWF_ERR_NAN, "non-finite residual in CG iteration"};
@@ -145,6 +166,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
     const bool diverging = rr_new > 1e4 * rr_true;
     if (MIXED && (rr_new < delta * delta * rr_max || rr_new <= target || diverging)) {
       // reliable update: fold the FP32 increment into the FP64 solution, recompute r in FP64
+      flush();
       DWF_CHECK_LAUNCH(launch_accumulate<PX>(x, xl, n5, Ls, s));
       rr_new = true_residual();
       DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
@@ -168,6 +190,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
     rr = rr_new;
     if (rr > rr_max) rr_max = rr;
   }
+  flush();
   if (MIXED) DWF_CHECK_LAUNCH(launch_accumulate<PX>(x, xl, n5, Ls, s));
   st->iters += it;
   st->last_rel = std::sqrt(rr / rhs2);
@@ -493,8 +516,8 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
         continue;
       }
       const double beta = restart ? 0.0 : rr_new / b.rr;
-      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(chview<Pi>(b.r, b.g, Ls), hview<Pi>(b.pv, b.g, Ls), beta,
-                                             sc + k * S_COUNT, rr_new, n5, Ls, s));
+      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(chview<Pi>(b.r, b.g, Ls), chview<Pi>(b.pv, b.g, Ls),
+                                             hview<Pi>(b.pv, b.g, Ls), beta, sc + k * S_COUNT, rr_new, n5, Ls, s));
       b.rr = rr_new;
       if (b.rr > b.rr_max) b.rr_max = b.rr;
     }
