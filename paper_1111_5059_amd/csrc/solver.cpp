@@ -90,7 +90,14 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
     return 0;
   }
   const double target = tol_n * tol_n * rhs2;
-  double rr = true_residual();
+  // a zero initial guess (the inner solves of MADWF) needs no operator application: r = rhs
+  double rr;
+  if (norm2_sync<P64>(ctx, cv(x), g, Ls) == 0.0) {
+    DWF_CHECK_HIP(hipMemcpyAsync(rhi.data, rhs.data, hb64, hipMemcpyDeviceToDevice, s));
+    rr = rhs2;
+  } else {
+    rr = true_residual();
+  }
   if (!std::isfinite(rr)) throw Error{DWF_ERR_NAN, "non-finite residual at CG start"};
   if (rr <= target) return 0;
 
@@ -109,7 +116,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   // xl += alpha_k p_k is applied KX iterations at a time (one pass that reads the KX
   // directions and xl once, instead of xl read and written in every iteration), and before
   // every reliable update and at the end.  The alphas wait in the scalar history slots.
-  constexpr int KX = 4;
+  constexpr int KX = 8;
   static_assert(KX >= 2 && KX <= XFLUSH_MAX, "direction ring");
   Half<Pi> pr[KX];
   for (int j = 0; j < KX; ++j) pr[j] = hview<Pi>(ws_get(ctx, tag + ".p" + std::to_string(j) + "." + pname(Pi::ID), hbi), g, Ls);
