@@ -733,8 +733,12 @@ int madwf(dwf_ctx* ctx, const dwf_params& pt, const dwf_params& pi, const void* 
       DWF_CHECK_LAUNCH(launch_slice_copy(CH(yp, par, Lp, hbp), Lp, 0, H(c, par, L, hb), L, 0, -1.0, ns, s));
     pshift(c, w, 0, L, hb);
     opt.full(CH(w, 0, L, hb), CH(w, 1, L, hb), H(t, 0, L, hb), H(t, 1, L, hb), false);
-    // w = P^-1 D(1)^-1 t
-    DWF_CHECK_LAUNCH(launch_zero(w, 2 * hb, s));
+    // w = P^-1 D(1)^-1 t, started from P (0, c_2, .., c_L): for any y with y_1 = 0,
+    // P^-1 D(1)^-1 D(m) P y = y (Sec. 4: the PV-transformed operator is the identity off the
+    // first slice), so that guess is exact except for the part D(m) P (-y'_1, 0, .., 0) of t
+    for (int par = 0; par < 2; ++par)
+      DWF_CHECK_LAUNCH(launch_slice_copy(CH(yp, par, Lp, hbp), Lp, 0, H(c, par, L, hb), L, 0, 0.0, ns, s));
+    pshift(c, w, 0, L, hb);
     std::memset(&si, 0, sizeof(si));
     solve_full(ctx, ppv, U64, t, w, info->tol_pv, maxit, delta, "pv", &si);
     info->pv_iters += si.iters; info->n_pv++; info->seconds_pv += si.seconds;
