@@ -6,8 +6,8 @@ python -m paper_1111_5059_amd.profiling traffic <fetch_counter_collection.csv> <
 
 ``traffic`` converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every hop and
 fifth-dimension kernel variant in the run into HBM bytes per launch, each scaled by what the
-same counter reads for a plain device copy of a known size (the largest copy kernel in the
-same run), and records the hash of the kernel sources so that a later kernel change
+same counter reads for a plain device copy of a known size (the last of the largest copy
+kernels in the same run), and records the hash of the kernel sources so that a later kernel change
 invalidates the figures.
 """
 import csv
@@ -83,16 +83,18 @@ def per_kernel(path, counter):
 
 
 def copy_counter(path, counter):
-    """counter of the largest device copy in the run (torch's copy kernel)"""
+    """counter of the calibration copy: the last dispatch of the largest-grid device copy kernel
+    (``bench.py --only-hop`` ends with a 1 GiB device copy; solver copies of the same grid size
+    may come earlier in the run)"""
     best = None
     for r in _rows(path):
         if _col(r, "Counter_Name") != counter:
             continue
         name = _col(r, "Kernel_Name")
-        if "copy" in name.lower() or "Copy" in name:
-            g = int(_col(r, "Grid_Size"))
-            if best is None or g > best[0]:
-                best = (g, float(_col(r, "Counter_Value")), name)
+        if "copy" in name.lower():
+            g, d = int(_col(r, "Grid_Size")), int(_col(r, "Dispatch_Id"))
+            if best is None or (g, d) > (best[0], best[3]):
+                best = (g, float(_col(r, "Counter_Value")), name, d)
     return best
 
 
