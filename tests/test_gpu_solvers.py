@@ -75,6 +75,25 @@ def test_cg_ne_not_converged_reports(env):
     assert not info["converged"] and info["iters"] <= 5 and info["true_rel_resid"] > 1e-10
 
 
+@pytest.mark.parametrize("k", [3, 8, 11])
+def test_partial_cg_iterate_matches_oracle(env, ora, k):
+    """After exactly k iterations from zero (not converged), the FP64 CG iterate -- whose increment
+    the library sums eight iterations at a time from a ring of directions -- is the oracle's CGNR
+    iterate after k iterations; an FP32 run (FP64 reliable updates) stays close to it."""
+    dwf, ctx = env
+    dims, Ls, U, b = cfg1()
+    xo, info_o = ora.solve(ora.params(dims, Ls), U, b, tol=1e-14, maxit=k)
+    assert info_o["iters"] == k and not info_o["converged"]
+    lat = dwf.Lattice(ctx, dims, Ls)
+    Ug, bg = lat.pack_gauge(U), lat.pack(b)
+    for prec, tol in ((dwf.FP64, 1e-11), (dwf.FP32, 1e-4)):
+        xg = lat.zeros(dwf.KIND_FULL)
+        info = dwf.cg_ne(ctx, lat.params(prec_inner=prec), Ug, bg, xg, tol=1e-14, maxit=k)
+        assert info["iters"] == k and not info["converged"], (prec, info)
+        assert rel_err(lat.unpack_np(xg), xo) < tol, (prec, k)
+        assert abs(info["true_rel_resid"] - info_o["true_rel_resid"]) < 10 * tol * info_o["true_rel_resid"]
+
+
 def test_cg_ne_zero_source(env):
     dwf, ctx = env
     dims, Ls = (2, 2, 2, 2), 4
