@@ -352,17 +352,17 @@ __device__ __forceinline__ void hop_dir(const HopArgs<P>& a, const int* nb, cons
   }
 }
 
-// FP16: at least 5 waves per SIMD (at most 102 VGPRs), since the kernel is bound by memory
-// latency; not with the fused CG step or several slices per thread, whose extra operands
-// would then spill
-template <typename P, int NS, bool CG>
-constexpr int hop_min_waves() { return std::is_same<P, P16>::value && NS == 1 && !CG ? 5 : 1; }
+// FP16 with one slice per thread: at least 5 waves per SIMD (at most 102 VGPRs), since the
+// kernel is bound by the latency of its gathers; 4 for the fused CG step without an epilogue
+// matrix, which would spill at 5.  Several slices per thread keep the default.
+template <typename P, int NS, int EPI, bool CG>
+constexpr int hop_min_waves() { return std::is_same<P, P16>::value && NS == 1 ? (CG && EPI == 0 ? 4 : 5) : 1; }
 
 // ST: neighbour spinors staged through LDS (FP16, compile-time Ls, one slice per lane, no
 // prologue, spb = 256 / Ls); its links are staged too (LL), so that the direction loop issues
 // no other vector-memory loads than the copies
 template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST>
-__global__ void __launch_bounds__(256, (hop_min_waves<P, NS, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
+__global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
