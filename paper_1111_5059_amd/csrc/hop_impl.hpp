@@ -209,27 +209,45 @@ __device__ __forceinline__ float load_input_f16_pro(const HopArgs<P16>& a, long 
   return m;
 }
 
-template <int MU, int SG, int NS, bool PRO, bool PAIRED>
-__device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const __half2* L, int D, int s0, int tps,
-                                            const ProCoef<float> (&pro)[NS], cx<float> (&acc)[NS][12]) {
-  f16x2 Uc[9], Us[9];
-  links_f16<PAIRED>(L, D, Uc, Us);
+// The FP16 direction step in two stages: the neighbour's spinors (with the prologue, if any)
+// and norms are loaded first, the projection, SU(3) product and reconstruction follow.  The
+// kernel issues the loads of the next direction before the arithmetic of the current one, so
+// that two directions' gathers are always in flight (left to itself the compiler kept fewer
+// loads outstanding in some variants: dagger hops waited at vmcnt 3 on average, the others at 8).
+template <int NS>
+struct F16In {
+  f16x2 psi[NS][12];
+  float n[NS];
+};
+
+template <int NS, bool PRO>
+__device__ __forceinline__ void load_dir_f16(const HopArgs<P16>& a, long y, int s0, int tps,
+                                             const ProCoef<float> (&pro)[NS], F16In<NS>& in) {
   const int Ls = a.Ls;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     const int s = s0 + j * tps;
-    f16x2 psi[12], h[6];
-    float n;
     if constexpr (PRO) {
-      n = load_input_f16_pro(a, y, s, pro[j], psi);
+      in.n[j] = load_input_f16_pro(a, y, s, pro[j], in.psi[j]);
     } else {
       const __half2* p = a.in.data + size_t(y) * 12 * Ls + s;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) psi[k] = as_f16x2(p[k * Ls]);
-      n = a.in.norm[size_t(y) * Ls + s];
+      for (int k = 0; k < 12; ++k) in.psi[j][k] = as_f16x2(p[k * Ls]);
+      in.n[j] = a.in.norm[size_t(y) * Ls + s];
     }
-    n *= a.scale;  // the hop's overall scale folded in
-    project_f16<MU, SG>(psi, h);
+  }
+}
+
+template <int MU, int SG, int NS, bool PAIRED>
+__device__ __forceinline__ void apply_dir_f16(const HopArgs<P16>& a, const __half2* L, int D, const F16In<NS>& in,
+                                              cx<float> (&acc)[NS][12]) {
+  f16x2 Uc[9], Us[9];
+  links_f16<PAIRED>(L, D, Uc, Us);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    f16x2 h[6];
+    const float n = in.n[j] * a.scale;  // the hop's overall scale folded in
+    project_f16<MU, SG>(in.psi[j], h);
     float re[6], im[6];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -240,6 +258,27 @@ __device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const
       }
     reconstruct_fma<MU, SG>(re, im, n, acc[j]);
   }
+}
+
+template <int MU, int SG, int NS, bool PRO, bool PAIRED>
+__device__ __forceinline__ void hop_dir_f16(const HopArgs<P16>& a, long y, const __half2* L, int D, int s0, int tps,
+                                            const ProCoef<float> (&pro)[NS], cx<float> (&acc)[NS][12]) {
+  F16In<NS> in;
+  load_dir_f16<NS, PRO>(a, y, s0, tps, pro, in);
+  apply_dir_f16<MU, SG, NS, PAIRED>(a, L, D, in, acc);
+}
+
+// the eight FP16 directions with the loads of direction D + 1 issued before the arithmetic of D
+template <int D, bool DAG, bool PRO, int NS, bool PAIRED>
+__device__ __forceinline__ void hop_dirs_f16(const HopArgs<P16>& a, const int* nb, const __half2* L, int s0, int tps,
+                                             const ProCoef<float> (&pro)[NS], F16In<NS>& cur, F16In<NS>& nxt,
+                                             cx<float> (&acc)[NS][12]) {
+  constexpr int MU = D & 3;
+  constexpr bool FWD = D < 4;
+  constexpr int SG = (FWD != DAG) ? -1 : +1;
+  if constexpr (D + 1 < 8) load_dir_f16<NS, PRO>(a, nb[D + 1], s0, tps, pro, nxt);
+  apply_dir_f16<MU, SG, NS, PAIRED>(a, L, D, cur, acc);
+  if constexpr (D + 1 < 8) hop_dirs_f16<D + 1, DAG, PRO, NS, PAIRED>(a, nb, L, s0, tps, pro, nxt, cur, acc);
 }
 
 // ------------------------------------------------------------------ LDS-staged neighbour spinors
@@ -440,14 +479,22 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_ke
     ProCoef<R> pro[NS];
 #pragma unroll
     for (int j = 0; j < NS; ++j) pro[j] = pro_coef<P, PRO>(ak, s0 + j * tps);
-    hop_dir<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<1, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<2, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<3, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<4, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<5, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<6, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
-    hop_dir<7, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    if constexpr (std::is_same<P, P16>::value) {
+      F16In<NS> b0, b1;
+      load_dir_f16<NS, PRO>(ak, nb[0], s0, tps, pro, b0);
+      hop_dirs_f16<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, b0, b1, acc);
+    } else {
+      // (FP64 / FP32: the same pipelining was measured slower for the prologue and epilogue
+      // variants, which already run at low occupancy)
+      hop_dir<0, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<1, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<2, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<3, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<4, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<5, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<6, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+      hop_dir<7, DAG, PRO, NS, PAIRED>(ak, nb, L, s0, tps, pro, acc);
+    }
   }
   if constexpr (!std::is_same<P, P16>::value) {  // (the FP16 path folds the scale into the norm)
 #pragma unroll
