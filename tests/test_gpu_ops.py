@@ -302,3 +302,31 @@ def test_traversal_tile_changes_nothing_but_the_order(env, ora):
     assert dwf.dwf_tune_tile_get(ctx, dims, 1) == default
     for dag in (False, True):
         assert np.array_equal(apply(dag), first[dag])
+
+
+@pytest.mark.parametrize("Ls", [8, 16, 32])
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("bc", [(1.0, 0.0), (1.5, 0.5)])
+def test_scan_epilogue_every_segment_length(env, ora, Ls, prec, bc):
+    """The recurrence form of the fifth-dimension blocks in FP32 arithmetic (cross-lane moves
+    within rows of 16 lanes, and across rows for Ls = 32), in the hop's epilogue (M_prec, M_prec^dag)
+    and in the standalone kernel (A^-1, A^-dag), against the oracle at every segment length."""
+    dwf, ctx = env
+    P = dwf.PREC_NAMES[prec]
+    dims = (4, 2, 2, 4)
+    U, psi = make(dims, Ls, 850 + Ls)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.05, b=bc[0], c=bc[1], tbc=1)
+    po = ora.params(dims, Ls, mass=0.05, b=bc[0], c=bc[1], tbc=1)
+    Ug = lat.pack_gauge(U, P)
+    psio = mask(psi, dims, 1)
+    src = lat.pack(psio, dwf.KIND_ODD, P)
+    for dag in (False, True):
+        dst = lat.empty(dwf.KIND_ODD, P)
+        dwf.mobius_dslash(ctx, lat.params(P), Ug, src, dst, dwf.OP_MPREC, 1, dag)
+        err = rel_err(lat.unpack_np(dst, dwf.KIND_ODD, P), ora.mprec(po, U, psio, dagger=dag))
+        assert err < PREC_TOL[prec], ("mprec", dag, err)
+        dst = lat.empty(dwf.KIND_ODD, P)
+        dwf.mobius_dslash(ctx, lat.params(P), Ug, src, dst, dwf.OP_AINV, 1, dag)
+        ref = mask(ora.fifth(po, psio, "Ainv" + ("dag" if dag else "")), dims, 1)
+        err = rel_err(lat.unpack_np(dst, dwf.KIND_ODD, P), ref)
+        assert err < PREC_TOL[prec], ("Ainv", dag, err)
