@@ -160,7 +160,12 @@ int mobius_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* 
  * CG on the even-odd normal equations.  U: packed FP64 gauge.  x holds the
  * initial guess on entry.  p->prec_inner < FP64 runs the iterations in that
  * storage precision (FP32 arithmetic) with FP64 reliable updates, FP64 CG
- * scalars and an FP64 solution accumulator. */
+ * scalars and an FP64 solution accumulator.  Workspace (held by ctx from the
+ * first call until dwf_ctx_destroy): eight search directions, the residual and
+ * three temporaries as odd half fields of the iteration precision (one more for
+ * Moebius operators), an FP32 solution increment and eleven FP64 half fields
+ * (one FP64 half field at 24^3x64, Ls = 32: 2.7 GB; the whole set in FP16
+ * iterations about 40 GB). */
 int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info);
 
 /* Several right-hand sides solved together (the Hasenbusch mass ladder of Sec. 3):
