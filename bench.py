@@ -274,8 +274,8 @@ def main():
     ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
     ap.add_argument("--inner", default="fp16", choices=["fp16", "bf16", "fp32"])
     ap.add_argument("--n-dc", type=int, default=2)
-    ap.add_argument("--tol-mobius", type=float, default=3e-4)
-    ap.add_argument("--tol-pv", type=float, default=3e-5)
+    ap.add_argument("--tol-mobius", type=float, default=2e-4)
+    ap.add_argument("--tol-pv", type=float, default=2e-4)
     ap.add_argument("--pv-prec", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
     ap.add_argument("--final-prec", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"])
     ap.add_argument("--no-hop", action="store_true")
