@@ -173,6 +173,71 @@ def hasenbusch_ladder(dwf, ctx, prec="fp32", tol=1e-6):
             "iters": info["iters"], "iters_sequential": iters_seq, "S": info["S"]}
 
 
+def batched_cfg5(dwf, prec="fp32", tol=1e-10, eps=0.5):
+    """Mass-ladder right-hand sides on the 32^3 x 64, Ls = 16 lattice (Sec. 3: the masses a
+    Hasenbusch ladder needs): m in {0.005, 0.02, 0.1, 0.4} x 2 Gaussian sources = 8 solves of
+    D(m) x = b to a full-system true residual tol, first one at a time (cg_ne), then as one batched
+    CG (cg_ne_batched: every hop stage one launch for all unconverged right-hand sides, links
+    staged once per workgroup for all of them).  The two runs use separate contexts, so that their
+    workspaces (about 60 and 180 GB) are never held together."""
+    import torch
+    import synth
+    dims, Ls, masses = (32, 32, 32, 64), 16, [0.005, 0.02, 0.1, 0.4]
+    P = dwf.PREC_NAMES[prec]
+    t = time.perf_counter()
+    U = synth.random_links(dims, eps, synth.link_seed(5))
+    log(f"cfg5 links generated in {time.perf_counter() - t:.1f} s")
+
+    def setup():
+        ctx = dwf.Context()
+        lat = dwf.Lattice(ctx, dims, Ls, mass=masses[0])
+        U64 = lat.pack_gauge(U)
+        rng = torch.Generator(device="cuda")
+        rng.manual_seed(synth.source_seed(5))
+        bs = [lat.empty(dwf.KIND_FULL) for _ in range(2)]
+        for b in bs:
+            b.view(torch.float64).normal_(generator=rng)  # Gaussian components, seeded on the device
+        return ctx, lat, U64, bs
+
+    rhs = [(m, k) for m in masses for k in range(2)]
+    ctx, lat, U64, bs = setup()
+    dwf.cg_ne(ctx, lat.params(prec_inner=P), U64, bs[0], lat.zeros(dwf.KIND_FULL), tol=tol, maxit=2)  # allocations
+    torch.cuda.synchronize()
+    seq, t = [], time.perf_counter()
+    for m, k in rhs:
+        x = lat.zeros(dwf.KIND_FULL)
+        seq.append(dwf.cg_ne(ctx, lat.params(mass=m, prec_inner=P), U64, bs[k], x, tol=tol))
+        del x
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    log(f"cfg5: 8 solves one at a time {t_seq:.2f} s")
+    del lat, U64, bs
+    ctx.close()
+    torch.cuda.empty_cache()
+
+    ctx, lat, U64, bs = setup()
+    xs = [lat.zeros(dwf.KIND_FULL) for _ in rhs]
+    pars = [lat.params(mass=m, prec_inner=P) for m, _ in rhs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bat = dwf.cg_ne_batched(ctx, pars, U64, [bs[k] for _, k in rhs], xs, tol=tol)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t
+    log(f"cfg5: 8 solves batched {t_bat:.2f} s")
+    del lat, U64, bs, xs
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"metric": "time to 1e-10 for 8 right-hand sides, batched CG vs one at a time", "unit": "s",
+            "workload": f"Shamir DWF 32^3x64 Ls=16 M5=1.8, masses {masses} x 2 Gaussian sources, random SU(3) "
+                        f"links eps={eps}, {prec} iterations with FP64 reliable updates, true residual {tol:g}",
+            "batched_s": t_bat, "sequential_s": t_seq, "speedup": t_seq / t_bat,
+            "per_rhs": [{"mass": m, "source": k, "iters_sequential": a["iters"], "iters_batched": c["iters"],
+                         "true_rel_resid_sequential": a["true_rel_resid"], "true_rel_resid_batched": c["true_rel_resid"],
+                         "seconds_sequential": a["seconds"]}
+                        for (m, k), a, c in zip(rhs, seq, bat)],
+            "converged": all(a["converged"] for a in seq) and all(c["converged"] for c in bat)}
+
+
 def fgi_measure(dwf, ctx, prec="fp32", tol=1e-8, n_steps=2, tau=0.1, beta=5.7, eps=0.5, mass=0.01):
     """Force-gradient-integrator trajectory (Sec. 2) on the 16^3 x 32, Ls = 16 force lattice
     (m = 0.01): wall time per step, energy violation, and the iterations the force-gradient
@@ -284,6 +349,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the Hasenbusch-ladder force measurement")
+    ap.add_argument("--batched-cfg5", action="store_true",
+                    help="only the 8-right-hand-side batched solve on 32^3x64, Ls=16 (about 180 GB of HBM; "
+                         "prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 "
@@ -293,6 +361,11 @@ def main():
     import torch
     import paper_1111_5059_amd as dwf
     import synth
+
+    if args.batched_cfg5:
+        torch.cuda.set_device(0)
+        print(json.dumps(batched_cfg5(dwf)))
+        return
 
     dims, L, mass, eps, Lp, bm, cm, desc = WORKLOADS[args.workload]
     cfgno = {"cfg1": 1, "cfg2": 2, "cfg3": 3}[args.workload]
