@@ -13,7 +13,9 @@
 
 namespace dwf {
 
-template <typename P, bool DAG, bool PRO, bool EPI>
+// LS > 0: every group has Ls = LS and the epilogue runs in recurrence form (one slice per
+// lane, the site's LS lanes one wave segment); LS = 0: the dense Ls x Ls epilogue through LDS
+template <typename P, bool DAG, bool PRO, bool EPI, int LS>
 __global__ void __launch_bounds__(256) hop_multi_kernel(const MultiGroup<P>* groups, int ngroups,
                                                         const MultiRhs<P>* rhs) {
   using R = typename P::R;
@@ -23,7 +25,8 @@ __global__ void __launch_bounds__(256) hop_multi_kernel(const MultiGroup<P>* gro
   int gi = 0;
   while (gi + 1 < ngroups && (long)blockIdx.x >= groups[gi + 1].block_begin) ++gi;
   const MultiGroup<P> g = groups[gi];
-  const int Ls = g.Ls;
+  const int Ls = LS > 0 ? LS : g.Ls;
+  constexpr bool DENSE = EPI && LS == 0;
   const long bid = (long)blockIdx.x - g.block_begin;
   const int lsite = threadIdx.x / Ls;
   const int s0 = threadIdx.x - lsite * Ls;
@@ -31,7 +34,7 @@ __global__ void __launch_bounds__(256) hop_multi_kernel(const MultiGroup<P>* gro
   const bool active = (lsite < g.spb) && (slot < g.nsites);
   const long x = active ? (g.order ? long(g.order[slot]) : slot) : 0;
   // links of the workgroup's sites, staged once for all right-hand sides
-  S* llds = reinterpret_cast<S*>(smem_raw + (EPI ? size_t(g.spb) * 12 * Ls * sizeof(cx<R>) : 0));
+  S* llds = reinterpret_cast<S*>(smem_raw + (DENSE ? size_t(g.spb) * 12 * Ls * sizeof(cx<R>) : 0));
   for (int i = threadIdx.x; i < g.spb * 72; i += blockDim.x) {
     const int ls = i / 72;
     const long sl = bid * g.spb + ls;
@@ -68,7 +71,10 @@ __global__ void __launch_bounds__(256) hop_multi_kernel(const MultiGroup<P>* gro
     }
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[0][k] = q.scale * acc[0][k];
-    if constexpr (EPI) {
+    if constexpr (EPI && LS > 0) {
+      fifth_scan_apply<LS>(acc[0], s0, q.es);  // (all lanes: inactive ones hold zeros)
+    }
+    if constexpr (DENSE) {
       cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
       __syncthreads();  // the previous right-hand side's epilogue reads are complete
       if (active) {
@@ -130,11 +136,30 @@ size_t multi_lds_bytes(int spb, int Ls, bool epi) {
 
 // Validates every group's shape against the kernel's assumptions before launching:
 // spb * Ls <= 256 threads, LDS within 64 KiB, consistent block prefix.
+template <typename P, bool DAG, bool PRO, bool EPI>
+static void launch_multi_ls(int ls, long blocks, int threads, size_t lds, hipStream_t st, const MultiGroup<P>* d_groups,
+                            int ng, const MultiRhs<P>* d_rhs) {
+  switch (ls) {
+    case 8: hipLaunchKernelGGL((hop_multi_kernel<P, DAG, PRO, EPI, 8>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs); break;
+    case 16: hipLaunchKernelGGL((hop_multi_kernel<P, DAG, PRO, EPI, 16>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs); break;
+    case 32: hipLaunchKernelGGL((hop_multi_kernel<P, DAG, PRO, EPI, 32>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs); break;
+    default: hipLaunchKernelGGL((hop_multi_kernel<P, DAG, PRO, EPI, 0>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs); break;
+  }
+}
+
 template <typename P>
 int launch_hop_multi(const MultiGroup<P>* d_groups, const std::vector<MultiGroup<P>>& h_groups, const MultiRhs<P>* d_rhs,
-                     bool dagger, bool prologue, bool epi, hipStream_t st) {
+                     bool dagger, bool prologue, bool epi, hipStream_t st, bool scan) {
   if (h_groups.empty()) return 0;
   if (dagger && prologue) return -1;
+  // the recurrence form needs one Ls of 8, 16 or 32 for the whole launch (a compile-time segment)
+  int ls = 0;
+  if (epi && scan) {
+    ls = h_groups[0].Ls;
+    for (const auto& g : h_groups)
+      if (g.Ls != ls) ls = 0;
+    if (ls != 8 && ls != 16 && ls != 32) ls = 0;
+  }
   long blocks = 0;
   size_t lds = 0;
   int threads = 0;
@@ -142,28 +167,28 @@ int launch_hop_multi(const MultiGroup<P>* d_groups, const std::vector<MultiGroup
     if (g.Ls < 1 || g.spb < 1 || g.spb * g.Ls > 256 || g.nrhs < 1) return -1;
     if (g.block_begin != blocks) return -1;
     blocks += (g.nsites + g.spb - 1) / g.spb;
-    lds = std::max(lds, multi_lds_bytes<P>(g.spb, g.Ls, epi));
+    lds = std::max(lds, multi_lds_bytes<P>(g.spb, g.Ls, epi && ls == 0));
     threads = std::max(threads, g.spb * g.Ls);
   }
   if (lds > 65536) return -1;
   if (blocks <= 0) return 0;
   const int ng = int(h_groups.size());
   if (dagger) {
-    if (epi) hipLaunchKernelGGL((hop_multi_kernel<P, true, false, true>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs);
-    else hipLaunchKernelGGL((hop_multi_kernel<P, true, false, false>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs);
+    if (epi) launch_multi_ls<P, true, false, true>(ls, blocks, threads, lds, st, d_groups, ng, d_rhs);
+    else launch_multi_ls<P, true, false, false>(0, blocks, threads, lds, st, d_groups, ng, d_rhs);
   } else if (prologue) {
-    if (epi) hipLaunchKernelGGL((hop_multi_kernel<P, false, true, true>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs);
-    else hipLaunchKernelGGL((hop_multi_kernel<P, false, true, false>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs);
+    if (epi) launch_multi_ls<P, false, true, true>(ls, blocks, threads, lds, st, d_groups, ng, d_rhs);
+    else launch_multi_ls<P, false, true, false>(0, blocks, threads, lds, st, d_groups, ng, d_rhs);
   } else {
-    if (epi) hipLaunchKernelGGL((hop_multi_kernel<P, false, false, true>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs);
-    else hipLaunchKernelGGL((hop_multi_kernel<P, false, false, false>), dim3((unsigned)blocks), dim3(threads), lds, st, d_groups, ng, d_rhs);
+    if (epi) launch_multi_ls<P, false, false, true>(ls, blocks, threads, lds, st, d_groups, ng, d_rhs);
+    else launch_multi_ls<P, false, false, false>(0, blocks, threads, lds, st, d_groups, ng, d_rhs);
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 #define DWF_INST_MULTI(P)                                                                                        \
   template int launch_hop_multi<P>(const MultiGroup<P>*, const std::vector<MultiGroup<P>>&, const MultiRhs<P>*, \
-                                   bool, bool, bool, hipStream_t);                                              \
+                                   bool, bool, bool, hipStream_t, bool);                                        \
   template size_t multi_lds_bytes<P>(int, int, bool);
 
 DWF_INST_MULTI(P64)

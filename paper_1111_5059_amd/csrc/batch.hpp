@@ -28,13 +28,17 @@ struct MultiRhs {
   CHalf<P> x;
   typename P::R ax, scale, pb, pc, pm;
   double* norm_partials;  // one FP64 partial per workgroup of the group, or nullptr
+  FifthScan<typename P::R> es;  // E in recurrence form (used when every right-hand side of the
+  int scan = 0;                 // launch has it and the groups share Ls = 8, 16 or 32)
 };
 
 template <typename P>
 size_t multi_lds_bytes(int spb, int Ls, bool epi);
 
+// scan: every right-hand side carries its epilogue in recurrence form (MultiRhs::scan); the
+// launch then applies it with wave-segment scans when all groups share Ls = 8, 16 or 32
 template <typename P>
 int launch_hop_multi(const MultiGroup<P>* d_groups, const std::vector<MultiGroup<P>>& h_groups, const MultiRhs<P>* d_rhs,
-                     bool dagger, bool prologue, bool epi, hipStream_t st);
+                     bool dagger, bool prologue, bool epi, hipStream_t st, bool scan = false);
 
 }  // namespace dwf

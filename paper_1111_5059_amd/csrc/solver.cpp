@@ -393,6 +393,18 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
   }
   const bool moebius = !(S[0].p.b == 1.0 && S[0].p.c == 0.0);
   std::vector<int> hop_blocks(K, 0);
+  bool scan_st[4] = {false, false, false, false};  // every right-hand side of the stage has its scan form
+  // the epilogue of slot `slot` of system b in recurrence form
+  auto scan_of = [&](const BatchSys& b, int slot, FifthScan<R>& out) -> bool {
+    FifthScan<double> e;
+    if (!fifth_scan(b.p.Ls, b.p.M5, b.p.mass, b.p.b, b.p.c, slot, &e)) return false;
+    out.m = R(e.m);
+    for (int ch = 0; ch < 2; ++ch) {
+      const FifthChir<double>& q = e.ch[ch];
+      out.ch[ch] = FifthChir<R>{R(q.a1), R(q.b1), R(q.inv_alpha), R(q.a), R(q.corr), q.d1, q.d2, q.has_inv};
+    }
+    return true;
+  };
   auto build_tables = [&]() {
     // group active systems by (lattice, links): consecutive entries of one group share links
     std::vector<int> order_k;
@@ -409,6 +421,7 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
     for (int st = 0; st < 4; ++st) {
       hg[st].clear();
       hr[st].clear();
+      scan_st[st] = true;
       const int out_par = (st == 0 || st == 2) ? 0 : 1;
       long blocks = 0;
       for (size_t j = 0; j < keys.size(); ++j) {
@@ -456,6 +469,11 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
             Q.E = moebius ? E + size_t(E_FDAG) * 2 * ls2 : nullptr; Q.scale = R(-0.25);
             Q.x = chview<Pi>(b.q, b.g, Ls); Q.ax = R(1);
           }
+          if (Q.E) {
+            const int slot = int((Q.E - E) / (2 * ls2));
+            Q.scan = scan_of(b, slot, Q.es) ? 1 : 0;
+            if (!Q.scan) scan_st[st] = false;
+          }
           hr[st].push_back(Q);
         }
       }
@@ -471,8 +489,8 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
   int it = 0;
   while (nactive > 0 && it < maxit) {
     // q = M p (one launch per stage for all right-hand sides), alpha = rr / |q|^2
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[0], hg[0], dr[0], false, moebius, true, s));
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[1], hg[1], dr[1], false, moebius, true, s));
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[0], hg[0], dr[0], false, moebius, true, s, scan_st[0]));
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[1], hg[1], dr[1], false, moebius, true, s, scan_st[1]));
     for (int k = 0; k < K; ++k) {
       if (!S[k].active) continue;
       BatchSys& b = S[k];
@@ -482,8 +500,8 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
                                         reinterpret_cast<const R*>(b.E) + size_t(E_AINVDAG) * 2 * b.p.Ls * b.p.Ls,
                                         nullptr, CHalf<Pi>{nullptr, nullptr}, R(0), b.g->nsites, b.p.Ls, nullptr, s));
     }
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[2], hg[2], dr[2], true, false, true, s));
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[3], hg[3], dr[3], true, false, moebius, s));
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[2], hg[2], dr[2], true, false, true, s, scan_st[2]));
+    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[3], hg[3], dr[3], true, false, moebius, s, scan_st[3]));
     for (int k = 0; k < K; ++k) {
       if (!S[k].active) continue;
       BatchSys& b = S[k];
