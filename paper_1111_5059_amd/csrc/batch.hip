@@ -114,12 +114,26 @@ __global__ void __launch_bounds__(256) hop_multi_kernel(const MultiGroup<P>* gro
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[0][k] = acc[0][k] + q.ax * xv[k];
       }
-      if (q.norm_partials) {
+      if (q.cg_r.data) {
+        // r -= alpha v: the CG residual update of this right-hand side on the site
+        const R alpha = R(q.cg_sc[S_ALPHA]);
+        cx<R> rv[12];
+        load_spinor<P>(CHalf<P>{q.cg_r.data, q.cg_r.norm}, x, s0, Ls, rv);
 #pragma unroll
-        for (int k = 0; k < 12; ++k)
-          nrm += double(acc[0][k].re) * double(acc[0][k].re) + double(acc[0][k].im) * double(acc[0][k].im);
+        for (int k = 0; k < 12; ++k) rv[k] = {rv[k].re - alpha * acc[0][k].re, rv[k].im - alpha * acc[0][k].im};
+        store_spinor<P>(q.cg_r, x, s0, Ls, rv);
+        if (q.norm_partials) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) nrm += double(rv[k].re) * double(rv[k].re) + double(rv[k].im) * double(rv[k].im);
+        }
+      } else {
+        if (q.norm_partials) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k)
+            nrm += double(acc[0][k].re) * double(acc[0][k].re) + double(acc[0][k].im) * double(acc[0][k].im);
+        }
+        store_spinor<P>(q.out, x, s0, Ls, acc[0]);
       }
-      store_spinor<P>(q.out, x, s0, Ls, acc[0]);
     }
     if (q.norm_partials) {
       const double t = block_sum(nrm, red);

@@ -30,6 +30,10 @@ struct MultiRhs {
   double* norm_partials;  // one FP64 partial per workgroup of the group, or nullptr
   FifthScan<typename P::R> es;  // E in recurrence form (used when every right-hand side of the
   int scan = 0;                 // launch has it and the groups share Ls = 8, 16 or 32)
+  // CG step fused into the last hop of M^dag M p (cg_r.data == nullptr: none): the result v is
+  // not stored; r -= alpha v with alpha = cg_sc[S_ALPHA], norm_partials of the new |r|^2
+  Half<P> cg_r = {nullptr, nullptr};
+  const double* cg_sc = nullptr;
 };
 
 template <typename P>

@@ -464,10 +464,13 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
           } else if (st == 2) {  // te = A^-dag F^dag H^dag_eo (A^-dag q)   [A^-dag q is in Ap]
             Q.in = chview<Pi>(b.Ap, b.g, Ls); Q.out = hview<Pi>(b.te, b.g, Ls);
             Q.E = E + size_t(E_AINVDAG_FDAG) * 2 * ls2; Q.scale = R(1);
-          } else {  // Ap = q - 1/4 F^dag H^dag_oe te
+          } else {  // r -= alpha (q - 1/4 F^dag H^dag_oe te), |r|^2   (M^dag q not stored)
             Q.in = chview<Pi>(b.te, b.g, Ls); Q.out = hview<Pi>(b.Ap, b.g, Ls);
             Q.E = moebius ? E + size_t(E_FDAG) * 2 * ls2 : nullptr; Q.scale = R(-0.25);
             Q.x = chview<Pi>(b.q, b.g, Ls); Q.ax = R(1);
+            Q.cg_r = hview<Pi>(b.r, b.g, Ls);
+            Q.cg_sc = sc + size_t(k) * S_COUNT;
+            Q.norm_partials = part + size_t(k) * pstride;
           }
           if (Q.E) {
             const int slot = int((Q.E - E) / (2 * ls2));
@@ -494,7 +497,7 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
     for (int k = 0; k < K; ++k) {
       if (!S[k].active) continue;
       BatchSys& b = S[k];
-      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, hop_blocks[k], 1, sc + k * S_COUNT, S_QQ, 1, s));
+      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, hop_blocks[k], 1, sc + k * S_COUNT, S_QQ, 1, s, 0));
       // A^-dag q into Ap (consumed by the next stage before Ap is overwritten)
       DWF_CHECK_LAUNCH(launch_fifth<Pi>(chview<Pi>(b.q, b.g, b.p.Ls), hview<Pi>(b.Ap, b.g, b.p.Ls),
                                         reinterpret_cast<const R*>(b.E) + size_t(E_AINVDAG) * 2 * b.p.Ls * b.p.Ls,
@@ -507,10 +510,13 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
       BatchSys& b = S[k];
       const int Ls = b.p.Ls;
       const long n5 = b.g->nsites * Ls;
-      DWF_CHECK_LAUNCH((launch_cg_update<Pi, PX>(hview<PX>(b.xl, b.g, Ls), chview<Pi>(b.pv, b.g, Ls), hview<Pi>(b.r, b.g, Ls),
-                                                  chview<Pi>(b.Ap, b.g, Ls), sc + k * S_COUNT, n5, Ls,
-                                                  part + size_t(k) * pstride, s)));
-      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, reduction_blocks(n5), 1, sc + k * S_COUNT, S_RRNEW, 0, s));
+      // |r|^2 from the partials of the last stage; xl += alpha p (alpha kept in history slot 0)
+      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, hop_blocks[k], 1, sc + k * S_COUNT, S_RRNEW, 0, s));
+      XFlush<Pi> f;
+      f.p[0] = chview<Pi>(b.pv, b.g, Ls);
+      f.slot[0] = 0;
+      f.n = 1;
+      DWF_CHECK_LAUNCH((launch_xflush<Pi, PX>(hview<PX>(b.xl, b.g, Ls), f, sc + k * S_COUNT, n5, Ls, s)));
     }
     DWF_CHECK_HIP(hipMemcpyAsync(hsc.data(), sc, sizeof(double) * hsc.size(), hipMemcpyDeviceToHost, s));
     DWF_CHECK_HIP(hipStreamSynchronize(s));
