@@ -175,50 +175,7 @@ int launch_convert(CHalf<Pi> in, Half<Po> out, long n5, int Ls, hipStream_t st) 
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// x += alpha p ; r -= alpha Ap ; partial |r|^2
-template <typename P, typename Px>
-__global__ void __launch_bounds__(RED_THREADS) cg_update_kernel(Half<Px> xv, CHalf<P> p, Half<P> r, CHalf<P> Ap,
-                                                               const double* scalars, long n5, int Ls,
-                                                               double* partials) {
-  __shared__ double red[16];
-  using R = typename P::R;
-  using RX = typename Px::R;
-  const double alpha = scalars[S_ALPHA];
-  double acc = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n5; i += (long)gridDim.x * blockDim.x) {
-    const long xs = i / Ls;
-    const int s = int(i - xs * Ls);
-    cx<R> pv[12], rv[12], av[12];
-    cx<RX> xx[12];
-    load_spinor<P>(p, xs, s, Ls, pv);
-    load_spinor<P>(CHalf<P>{r.data, r.norm}, xs, s, Ls, rv);
-    load_spinor<P>(Ap, xs, s, Ls, av);
-    load_spinor<Px>(CHalf<Px>{xv.data, xv.norm}, xs, s, Ls, xx);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      xx[k].re = RX(double(xx[k].re) + alpha * double(pv[k].re));
-      xx[k].im = RX(double(xx[k].im) + alpha * double(pv[k].im));
-      rv[k].re = R(double(rv[k].re) - alpha * double(av[k].re));
-      rv[k].im = R(double(rv[k].im) - alpha * double(av[k].im));
-    }
-    store_spinor<Px>(xv, xs, s, Ls, xx);
-    store_spinor<P>(r, xs, s, Ls, rv);
-    acc += site_norm2<P>(rv);
-  }
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-
-template <typename P, typename Px>
-int launch_cg_update(Half<Px> x, CHalf<P> p, Half<P> r, CHalf<P> Ap, const double* scalars, long n5, int Ls,
-                     double* partials, hipStream_t st) {
-  const int nb = reduction_blocks(n5);
-  hipLaunchKernelGGL((cg_update_kernel<P, Px>), dim3(nb), dim3(RED_THREADS), 0, st, x, p, r, Ap, scalars, n5, Ls,
-                     partials);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
-}
-
-// p = r + beta p ; the first thread also records rr_new as the current |r|^2 (S_RR)
+// p_out = r + beta p_in ; the first thread also records rr_new as the current |r|^2 (S_RR)
 template <typename P>
 __global__ void __launch_bounds__(256) cg_pupdate_kernel(CHalf<P> r, CHalf<P> pin, Half<P> pout, double beta,
                                                           double* scalars, double rr_new, long n5, int Ls) {
@@ -566,14 +523,6 @@ template int launch_xflush<P32, P32>(Half<P32>, const XFlush<P32>&, const double
 template int launch_xflush<P16, P32>(Half<P32>, const XFlush<P16>&, const double*, long, int, hipStream_t);
 template int launch_xflush<PB16, P32>(Half<P32>, const XFlush<PB16>&, const double*, long, int, hipStream_t);
 
-template int launch_cg_update<P64, P64>(Half<P64>, CHalf<P64>, Half<P64>, CHalf<P64>, const double*, long, int,
-                                        double*, hipStream_t);
-template int launch_cg_update<P32, P32>(Half<P32>, CHalf<P32>, Half<P32>, CHalf<P32>, const double*, long, int,
-                                        double*, hipStream_t);
-template int launch_cg_update<P16, P32>(Half<P32>, CHalf<P16>, Half<P16>, CHalf<P16>, const double*, long, int,
-                                        double*, hipStream_t);
-template int launch_cg_update<PB16, P32>(Half<P32>, CHalf<PB16>, Half<PB16>, CHalf<PB16>, const double*, long, int,
-                                         double*, hipStream_t);
 template int launch_accumulate<P32>(Half<P64>, Half<P32>, long, int, hipStream_t);
 template int launch_accumulate<P16>(Half<P64>, Half<P16>, long, int, hipStream_t);
 template int launch_accumulate<P64>(Half<P64>, Half<P64>, long, int, hipStream_t);

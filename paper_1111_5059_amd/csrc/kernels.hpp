@@ -108,10 +108,6 @@ struct XFlush {
 };
 template <typename P, typename Px>
 int launch_xflush(Half<Px> x, const XFlush<P>& f, const double* scalars, long n5, int Ls, hipStream_t st);
-// x += alpha p  (x in Px, p in P);  r -= alpha Ap;  partials of |r|^2
-template <typename P, typename Px>
-int launch_cg_update(Half<Px> x, CHalf<P> p, Half<P> r, CHalf<P> Ap, const double* scalars, long n5, int Ls,
-                     double* partials, hipStream_t st);
 // p_out = r + beta p_in (p_in unused when beta = 0; it may be p_out) and scalars[S_RR] = rr_new
 template <typename P>
 int launch_cg_pupdate(CHalf<P> r, CHalf<P> pin, Half<P> pout, double beta, double* scalars, double rr_new, long n5,
