@@ -46,6 +46,34 @@ def test_mass_ladder_batch(env, ora, prec):
     assert rel_err(lat.unpack_np(xs[1]), lat.unpack_np(x1)) < 1e-7
 
 
+@pytest.mark.parametrize("Ls", [8, 12])
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_moebius_mass_ladder_batch(env, ora, Ls, prec):
+    """A Moebius ladder (b = 1.5, c = 0.5): input factor and F^dag epilogue in the batched stages,
+    the CG step fused into the last one; Ls = 8 takes the recurrence-form epilogue, Ls = 12 the
+    dense one.  Every solve reaches the full-system true residual against the oracle's operator."""
+    dwf, ctx = env
+    dims = (4, 4, 2, 4)
+    masses = [0.01, 0.1, 0.5]
+    U = synth.random_links(dims, 0.4, 1520 + Ls)
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8, b=1.5, c=0.5)
+    Ug = lat.pack_gauge(U)
+    P = dwf.PREC_NAMES[prec]
+    pars, bs, xs, srcs = [], [], [], []
+    for k, m in enumerate(masses):
+        b = synth.gaussian_spinor(dims, Ls, 1530 + k)
+        srcs.append(b)
+        pars.append(lat.params(mass=m, prec_inner=P))
+        bs.append(lat.pack(b))
+        xs.append(lat.zeros(dwf.KIND_FULL))
+    infos = dwf.cg_ne_batched(ctx, pars, Ug, bs, xs, tol=1e-10)
+    for k, (info, m) in enumerate(zip(infos, masses)):
+        assert info["converged"], (k, info)
+        po = ora.params(dims, Ls, M5=1.8, mass=m, b=1.5, c=0.5)
+        r = srcs[k] - ora.dwf(po, U, lat.unpack_np(xs[k]))
+        assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(srcs[k]), (k, m)
+
+
 def test_ragged_batch(env, ora):
     """8^4 Ls=8 and 12^2x4x6 Ls=12 (scaled-down versions of the ragged batch) in one solve."""
     dwf, ctx = env
