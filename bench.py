@@ -331,6 +331,32 @@ def cpu_baseline(workload, U, b_nat, fp64_iters, seconds_budget=25.0):
             "seconds_per_iteration": per_iter_full}
 
 
+def madwf_scan_run(dwf, dims=(32, 32, 32, 8), Ls=32, mass=0.005, eps=0.6, seed=6, inner_prec="fp32"):
+    """Figure 1 of the paper on synthetic fields: one defect-correction step per Moebius tolerance
+    and inner operator (L' = Ls/2 and 3Ls/8 with b = 1.5, c = 0.5, and a Shamir L' = Ls/2), with the
+    Moebius CG count, the true residual of the guess and the DWF CG count after it."""
+    import synth
+    from paper_1111_5059_amd import madwf_scan
+    ctx = dwf.Context()
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8, mass=mass)
+    U64 = lat.pack_gauge(synth.random_links(dims, eps, synth.link_seed(seed)))
+    b = lat.pack(synth.gaussian_spinor(dims, Ls, synth.source_seed(seed)))
+    ref = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.FP32), U64, b, lat.zeros(dwf.KIND_FULL), tol=1e-10)
+    log(f"zero-start DWF CG: {ref['iters']} iterations")
+    inners = [(Ls // 2, 1.5, 0.5), (3 * Ls // 8, 1.5, 0.5), (Ls // 2, 1.0, 0.0)]
+    tols = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6]
+    rows = []
+    for inner in inners:
+        rows += madwf_scan.scan(lat, U64, b, [inner], tols, prec_inner=dwf.PREC_NAMES[inner_prec])
+        for r in rows[-len(tols):]:
+            log(f"L'={r['Lp']} b={r['b']} c={r['c']} tol={r['tol_mobius']:.0e}: Moebius CG {r['mobius_iters']}, "
+                f"guess resid {r['guess_resid']:.2e}, DWF CG after {r['dwf_iters_after']}")
+    ctx.close()
+    return {"workload": f"Figure-1 scan, Shamir DWF {dims[0]}^3x{dims[3]} Ls={Ls} m={mass}, random SU(3) links "
+                        f"eps={eps}, Gaussian source, one defect-correction step, {inner_prec} Moebius solve",
+            "zero_start_dwf_iters": ref["iters"], "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +378,8 @@ def main():
     ap.add_argument("--batched-cfg5", action="store_true",
                     help="only the 8-right-hand-side batched solve on 32^3x64, Ls=16 (about 180 GB of HBM; "
                          "prints its own JSON line)")
+    ap.add_argument("--madwf-scan", action="store_true",
+                    help="only the Figure-1 Moebius-tolerance scan on 32^3x8, Ls=32 (prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 "
@@ -365,6 +393,10 @@ def main():
     if args.batched_cfg5:
         torch.cuda.set_device(0)
         print(json.dumps(batched_cfg5(dwf)))
+        return
+    if args.madwf_scan:
+        torch.cuda.set_device(0)
+        print(json.dumps(madwf_scan_run(dwf)))
         return
 
     dims, L, mass, eps, Lp, bm, cm, desc = WORKLOADS[args.workload]

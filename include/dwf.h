@@ -197,7 +197,12 @@ int mobius_accel_solve(dwf_ctx* ctx, const dwf_params* target, const dwf_params*
  *   out_kind 1: G_mu(x) = dS/dU in the convention dS = Re sum conj(G) dU.
  * tau_fg > 0: force-gradient step -- F1 at U, U' = exp(-tau^2/24 F1) U, then the
  * force at U' with its solve started from X(U); U is left unchanged.
- * *S receives the action at the configuration whose force is returned. */
+ * *S receives the action at the configuration whose force is returned.
+ * Each solve runs until the FP64 true residual ||phi - M^+M X|| / ||phi|| of the normal
+ * equations, recomputed after it, is at most info->tol (default 1e-12), within info->maxit
+ * iterations over all solves of the call; info->true_rel_resid receives the largest such
+ * residual.  Returns DWF_NOT_CONVERGED (F, S and x_io still written) if a solve stopped at
+ * maxit above the tolerance. */
 int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U_natural, const void* phi, void* F, double* S,
                   double tau_fg, int out_kind, void* x_io, dwf_solve_info* info);
 
@@ -211,7 +216,9 @@ int fermion_force(dwf_ctx* ctx, const dwf_params* p, const void* U_natural, cons
  * U (natural link layout) and P (momenta P = sum_a p_a T_a, same layout, traceless
  * anti-Hermitian), both device complex128, are updated in place; phi: packed FP64
  * odd half (held fixed).  The force solves run in p->prec_inner to the normal-
- * equation tolerance info->tol.  Fills H_start, H_end and the counters. */
+ * equation tolerance info->tol (FP64 true residual, as for fermion_force), each within
+ * info->maxit iterations.  Fills H_start, H_end and the counters; returns DWF_NOT_CONVERGED
+ * (the trajectory still completed) if a force solve stopped at maxit above the tolerance. */
 typedef struct {
   double beta;             /* plaquette coupling */
   double tau;              /* step size */

@@ -265,10 +265,12 @@ def fermion_force(ctx, p, U_natural, phi, F, tau_fg=0.0, out_kind=0, x_io=None, 
     info = SolveInfo()
     info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
     S = ctypes.c_double(0.0)
-    _check(lib().fermion_force(ctx.handle, ctypes.byref(p), _vp(_ptr(U_natural)), _vp(_ptr(phi)), _vp(_ptr(F)),
-                               ctypes.byref(S), float(tau_fg), int(out_kind), _vp(_ptr(x_io)), ctypes.byref(info)))
+    rc = _check(lib().fermion_force(ctx.handle, ctypes.byref(p), _vp(_ptr(U_natural)), _vp(_ptr(phi)), _vp(_ptr(F)),
+                                    ctypes.byref(S), float(tau_fg), int(out_kind), _vp(_ptr(x_io)),
+                                    ctypes.byref(info)), allow_not_converged=True)
     d = info.as_dict()
     d["S"] = S.value
+    d["converged"] = rc == DWF_OK
     return d
 
 
@@ -298,9 +300,11 @@ def hmc_fgi_trajectory(ctx, p, U_natural, P_natural, phi, beta, tau, n_steps, to
     info = HmcInfo()
     info.beta, info.tau, info.n_steps = float(beta), float(tau), int(n_steps)
     info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
-    _check(lib().hmc_fgi_trajectory(ctx.handle, ctypes.byref(p), _vp(_ptr(U_natural)), _vp(_ptr(P_natural)),
-                                    _vp(_ptr(phi)), ctypes.byref(info)))
-    return info.as_dict()
+    rc = _check(lib().hmc_fgi_trajectory(ctx.handle, ctypes.byref(p), _vp(_ptr(U_natural)), _vp(_ptr(P_natural)),
+                                         _vp(_ptr(phi)), ctypes.byref(info)), allow_not_converged=True)
+    d = info.as_dict()
+    d["converged"] = rc == DWF_OK
+    return d
 
 
 def dwf_tune_set(ctx, prec, Ls, sites_per_block, s_per_thread, xcd_remap=1, link_lds=1, kernel_id=0):

@@ -312,6 +312,7 @@ struct BatchSys {
   CHalf<P64> rhs;
   Half<P64> x;
   double rhs2 = 0, target = 0, rr = 0, rr_max = 0, rr_true = 0, tol_n = 0;
+  int cap = 0;  // iterations this system may still run
   bool active = false;
   SolveStats st;
   // inner vectors (storage precision of the solve)
@@ -374,7 +375,7 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
     b.rr = true_residual(b);
     if (!std::isfinite(b.rr)) throw Error{DWF_ERR_NAN, "non-finite residual at batched CG start"};
     b.rr_max = b.rr_true = b.rr;
-    if (b.rr <= b.target) { b.active = false; continue; }
+    if (b.rr <= b.target || b.cap <= 0) { b.active = false; continue; }
     Half<P64> rhi = hview<P64>(rhi_raw, b.g, Ls);
     Half<Pi> r = hview<Pi>(b.r, b.g, Ls);
     DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
@@ -546,6 +547,12 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
         changed = true;
         continue;
       }
+      if (b.st.iters >= b.cap) {  // out of iterations: stop with the current iterate
+        b.rr = rr_new;
+        b.active = false;
+        changed = true;
+        continue;
+      }
       const double beta = restart ? 0.0 : rr_new / b.rr;
       DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(chview<Pi>(b.r, b.g, Ls), chview<Pi>(b.pv, b.g, Ls),
                                              hview<Pi>(b.pv, b.g, Ls), beta, sc + k * S_COUNT, rr_new, n5, Ls, s));
@@ -613,8 +620,10 @@ int solve_batched(dwf_ctx* ctx, int nrhs, const dwf_params* P, const void* const
   int status = 0;
   for (int attempt = 0; attempt < 12; ++attempt) {
     std::vector<int> idx;
-    for (int k = 0; k < nrhs; ++k)
+    for (int k = 0; k < nrhs; ++k) {
+      if (!done[k] && S[k].st.iters >= maxit) done[k] = 2;  // the cap counts every attempt's iterations
       if (!done[k]) idx.push_back(k);
+    }
     if (idx.empty()) break;
     std::vector<BatchSys> run;
     run.reserve(idx.size());
@@ -623,6 +632,7 @@ int solve_batched(dwf_ctx* ctx, int nrhs, const dwf_params* P, const void* const
       c.p = S[k].p; c.g = S[k].g; c.U64 = S[k].U64; c.Ui = S[k].Ui;
       c.op64 = std::make_unique<Op<P64>>(ctx, S[k].g, S[k].p, S[k].U64);
       c.rhs = S[k].rhs; c.x = S[k].x; c.tol_n = S[k].tol_n;
+      c.cap = maxit - S[k].st.iters;
       run.push_back(std::move(c));
     }
     switch (prec) {
@@ -815,10 +825,17 @@ static void force_terms(dwf_ctx* ctx, const Op<P64>& op, const void* Unat, CHalf
                                 reinterpret_cast<double2*>(Fout), ctx->stream, coef, accumulate));
 }
 
+// S and the force at the links Unat.  X solves M^dag M X = phi to the normal-equation tolerance
+// tol_n, judged by the FP64 true residual ||phi - M^dag M X|| / ||phi|| recomputed after the
+// solve (the stop test of an FP64 recurrence uses its iterated residual); while it is above tol_n
+// the solve continues from X with a tightened stop, within maxit iterations in all.  *converged
+// turns false if it does not get there; *true_rel receives the largest true residual seen.
 static double force_at(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const void* phi, void* X, void* Fout,
-                       int kind, double tol_n, int maxit, double delta, SolveStats* st) {
+                       int kind, double tol_n, int maxit, double delta, SolveStats* st, bool* converged,
+                       double* true_rel) {
   const Geometry* g = geometry(ctx, p.dims, p.tbc);
   const int Ls = p.Ls;
+  const long n5 = g->nsites * Ls;
   const size_t hb = half_size<P64>(g, Ls);
   hipStream_t s = ctx->stream;
   void* U64 = ws_get(ctx, "force.U64", 2 * g->nsites * 72 * sizeof(double2));
@@ -827,16 +844,36 @@ static double force_at(dwf_ctx* ctx, const dwf_params& p, const void* Unat, cons
   Op<P64> op(ctx, g, p, U64);
   CHalf<P64> ph = chview<P64>(phi, g, Ls);
   Half<P64> Xo = hview<P64>(X, g, Ls);
-  normal_solve(ctx, p, U64, ph, Xo, tol_n, maxit, delta, "force.cg", st);
+  Half<P64> Y = hview<P64>(ws_get(ctx, "force.Y", hb), g, Ls);
+  Half<P64> tmp = hview<P64>(ws_get(ctx, "force.tmp", hb), g, Ls);
+  Half<P64> r = hview<P64>(ws_get(ctx, "force.r", hb), g, Ls);
+  Half<P64> tmp2 = hview<P64>(ws_get(ctx, "force.tmp2", hb), g, Ls);
+  const double p2 = norm2_sync<P64>(ctx, ph, g, Ls);
+  const int iters0 = st->iters;
+  double tol_try = tol_n, rel = 0.0;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    const int left = maxit - (st->iters - iters0);
+    if (attempt > 0 && left <= 0) break;
+    normal_solve(ctx, p, U64, ph, Xo, tol_try, std::max(0, left), delta, "force.cg", st);
+    op.mprec(cv(Xo), Y, tmp);  // Y = M X
+    // FP64 true residual of the normal equations, phi - M^dag Y
+    op.mprec_dag(cv(Y), r, tmp, tmp2);
+    DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, ph, -1.0, r, n5, Ls, s));
+    const double r2 = norm2_sync<P64>(ctx, cv(r), g, Ls);
+    rel = p2 > 0.0 ? std::sqrt(r2 / p2) : 0.0;
+    if (!std::isfinite(rel)) throw Error{DWF_ERR_NAN, "non-finite residual of the force solve"};
+    if (rel <= tol_n) break;
+    tol_try *= std::max(0.02, std::min(0.5, 0.5 * tol_n / rel));
+    st->restarts++;
+  }
+  *true_rel = std::max(*true_rel, rel);
+  if (rel > tol_n) *converged = false;
   // S = Re <phi, X>
   double* part = partials_buf(ctx);
   double* sc = scalars_buf(ctx);
-  DWF_CHECK_LAUNCH(launch_dot<P64>(ph, cv(Xo), g->nsites * Ls, Ls, part, s));
-  DWF_CHECK_LAUNCH(launch_reduce(part, reduction_blocks(g->nsites * Ls), 2, sc, S_TMP1, 0, s));
+  DWF_CHECK_LAUNCH(launch_dot<P64>(ph, cv(Xo), n5, Ls, part, s));
+  DWF_CHECK_LAUNCH(launch_reduce(part, reduction_blocks(n5), 2, sc, S_TMP1, 0, s));
   const double S = read_scalar(ctx, sc, S_TMP1);
-  Half<P64> Y = hview<P64>(ws_get(ctx, "force.Y", hb), g, Ls);
-  Half<P64> tmp = hview<P64>(ws_get(ctx, "force.tmp", hb), g, Ls);
-  op.mprec(cv(Xo), Y, tmp);  // Y = M X
   force_terms(ctx, op, Unat, cv(Xo), cv(Y), Fout, kind, 1.0, 0);
   return S;
 }
@@ -856,19 +893,21 @@ int fermion_force(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const voi
   else DWF_CHECK_LAUNCH(launch_zero(X, hb, s));
   SolveStats st;
   double Sv;
+  bool conv = true;
+  double rel = 0.0;
   if (tau_fg > 0.0) {
     // force-gradient step: F1 at U; U' = exp(-tau^2/24 F1) U; force at U' from X(U)
     const long nlinks = 4 * g->V;
     void* F1 = ws_get(ctx, "force.F1", nlinks * 9 * sizeof(double2));
     void* Up = ws_get(ctx, "force.Uprime", nlinks * 9 * sizeof(double2));
-    force_at(ctx, p, Unat, phi, X, F1, 0, tol, maxit, delta, &st);
+    force_at(ctx, p, Unat, phi, X, F1, 0, tol, maxit, delta, &st, &conv, &rel);
     const int it1 = st.iters;
     DWF_CHECK_LAUNCH(launch_fg_update(reinterpret_cast<const double2*>(F1), reinterpret_cast<const double2*>(Unat),
                                       tau_fg * tau_fg / 24.0, reinterpret_cast<double2*>(Up), nlinks, s));
-    Sv = force_at(ctx, p, Up, phi, X, F, out_kind, tol, maxit, delta, &st);
+    Sv = force_at(ctx, p, Up, phi, X, F, out_kind, tol, std::max(0, maxit - it1), delta, &st, &conv, &rel);
     if (info) info->iters_first = it1;
   } else {
-    Sv = force_at(ctx, p, Unat, phi, X, F, out_kind, tol, maxit, delta, &st);
+    Sv = force_at(ctx, p, Unat, phi, X, F, out_kind, tol, maxit, delta, &st, &conv, &rel);
   }
   if (x_io) DWF_CHECK_HIP(hipMemcpyAsync(x_io, X, hb, hipMemcpyDeviceToDevice, s));
   DWF_CHECK_HIP(hipStreamSynchronize(s));
@@ -876,11 +915,12 @@ int fermion_force(dwf_ctx* ctx, const dwf_params& p, const void* Unat, const voi
   if (info) {
     info->iters = st.iters;
     info->reliable_updates = st.reliable_updates;
-    info->true_rel_resid = st.last_rel;
+    info->restarts = st.restarts;
+    info->true_rel_resid = rel;
     info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
     info->wilson_apps = (long long)st.iters * Ls;
   }
-  return 0;
+  return conv ? DWF_OK : DWF_NOT_CONVERGED;
 }
 
 // ------------------------------------------------------------------ Hasenbusch quotients
@@ -926,6 +966,7 @@ int quotient_force(dwf_ctx* ctx, const dwf_params& p, int nq, const double* mass
     b.rhs = chview<P64>(chi[i], g, Ls);
     b.x = hview<P64>(X[i], g, Ls);
     b.tol_n = tol;
+    b.cap = maxit;
   }
   switch (p.prec_inner) {
     case DWF_FP64: cg_batched<P64>(ctx, B, maxit, delta); break;
@@ -977,8 +1018,8 @@ int quotient_force(dwf_ctx* ctx, const dwf_params& p, int nq, const double* mass
 // U' = exp(-tau^2/24 F(U)) U with its solve started from X(U) (force-gradient forecasting);
 // the other solves start from zero; the force at the end of a step opens the next one.
 static double total_force(dwf_ctx* ctx, const dwf_params& p, double beta, const void* U, const void* phi, void* X,
-                          void* F, double tol_n, int maxit, double delta, SolveStats* st) {
-  const double Sf = force_at(ctx, p, U, phi, X, F, 0, tol_n, maxit, delta, st);
+                          void* F, double tol_n, int maxit, double delta, SolveStats* st, bool* conv, double* rel) {
+  const double Sf = force_at(ctx, p, U, phi, X, F, 0, tol_n, maxit, delta, st, conv, rel);
   DWF_CHECK_LAUNCH(launch_gauge_force(reinterpret_cast<const double2*>(U), p.dims, beta, 1.0, 1,
                                       reinterpret_cast<double2*>(F), ctx->stream));
   return Sf;
@@ -1018,9 +1059,11 @@ int fgi_trajectory(dwf_ctx* ctx, const dwf_params& p, void* U, void* P, const vo
   double2* Pd = reinterpret_cast<double2*>(P);
   double2* Ud = reinterpret_cast<double2*>(U);
   SolveStats st;
+  bool conv = true;
+  double rel = 0.0;
   int evals = 0, fg_first = 0, fg_second = 0;
   DWF_CHECK_LAUNCH(launch_zero(X, hb, s));
-  double Sf = total_force(ctx, p, beta, U, phi, X, F, tol, maxit, delta, &st);
+  double Sf = total_force(ctx, p, beta, U, phi, X, F, tol, maxit, delta, &st, &conv, &rel);
   ++evals;
   info->H_start = hamiltonian(ctx, p, beta, U, P, Sf, nl);
   for (int step = 0; step < info->n_steps; ++step) {
@@ -1028,18 +1071,18 @@ int fgi_trajectory(dwf_ctx* ctx, const dwf_params& p, void* U, void* P, const vo
     DWF_CHECK_LAUNCH(launch_fg_update(Pd, Ud, -tau / 2.0, Ud, nl, s));  // U <- exp(tau/2 P) U
     DWF_CHECK_LAUNCH(launch_zero(X1, hb, s));
     int before = st.iters;
-    total_force(ctx, p, beta, U, phi, X1, F1, tol, maxit, delta, &st);
+    total_force(ctx, p, beta, U, phi, X1, F1, tol, maxit, delta, &st, &conv, &rel);
     fg_first += st.iters - before;
     // force-gradient step: U' = exp(-tau^2/24 F1) U, force at U' from X(U)
     DWF_CHECK_LAUNCH(launch_fg_update(reinterpret_cast<const double2*>(F1), Ud, tau * tau / 24.0,
                                       reinterpret_cast<double2*>(Up), nl, s));
     before = st.iters;
-    total_force(ctx, p, beta, Up, phi, X1, F1, tol, maxit, delta, &st);
+    total_force(ctx, p, beta, Up, phi, X1, F1, tol, maxit, delta, &st, &conv, &rel);
     fg_second += st.iters - before;
     DWF_CHECK_LAUNCH(launch_mom_update(Pd, reinterpret_cast<const double2*>(F1), 2.0 * tau / 3.0, nl, s));
     DWF_CHECK_LAUNCH(launch_fg_update(Pd, Ud, -tau / 2.0, Ud, nl, s));
     DWF_CHECK_LAUNCH(launch_zero(X, hb, s));
-    Sf = total_force(ctx, p, beta, U, phi, X, F, tol, maxit, delta, &st);
+    Sf = total_force(ctx, p, beta, U, phi, X, F, tol, maxit, delta, &st, &conv, &rel);
     DWF_CHECK_LAUNCH(launch_mom_update(Pd, reinterpret_cast<const double2*>(F), tau / 6.0, nl, s));
     evals += 3;
   }
@@ -1050,7 +1093,7 @@ int fgi_trajectory(dwf_ctx* ctx, const dwf_params& p, void* U, void* P, const vo
   info->fg_iters_first = fg_first;
   info->fg_iters_forecast = fg_second;
   info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
-  return 0;
+  return conv ? DWF_OK : DWF_NOT_CONVERGED;
 }
 
 }  // namespace dwf

@@ -7,17 +7,10 @@ each inner operator (L', b, c) and each Moebius tolerance it runs one MADWF step
 and records the Moebius CG count, the true residual of the guess, and the DWF CG count of
 the warm-started final solve to 1e-10; the zero-start DWF CG count is the reference.
 
-python -m paper_1111_5059_amd.madwf_scan [--dims 32 32 32 8] [--Ls 32] [--mass 0.005] [--eps 0.6]
-    [--inner-prec fp32|fp16|bf16]
-
-Defaults follow Figure 1: a 32^3 x 8 lattice with L = 32 and the inner L' = 16, b = 1.5,
-c = 0.5; the scan adds L' = 12 (Table 1's inner extent) and a Shamir inner (b = 1, c = 0) for
-comparison.  Output: one JSON object.
+The library call only: the inputs (links, source) are the caller's packed device fields.
+``python bench.py --madwf-scan`` runs the Figure-1 scan on synthetic fields (a 32^3 x 8 lattice
+with L = 32 and the inner L' = 16, b = 1.5, c = 0.5, plus L' = 12 and a Shamir inner operator).
 """
-import argparse
-import json
-import os
-import sys
 
 
 def scan(lat, U64, b, inners, tols, tol_pv=1e-8, prec_inner=None, prec_final=None):
@@ -38,42 +31,3 @@ def scan(lat, U64, b, inners, tols, tol_pv=1e-8, prec_inner=None, prec_final=Non
                         "pv_iters": info["pv_iters"], "wilson_apps": info["wilson_apps"],
                         "converged": info["converged"]})
     return out
-
-
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--dims", type=int, nargs=4, default=[32, 32, 32, 8])
-    ap.add_argument("--Ls", type=int, default=32)
-    ap.add_argument("--mass", type=float, default=0.005)
-    ap.add_argument("--eps", type=float, default=0.6)
-    ap.add_argument("--seed", type=int, default=6)
-    ap.add_argument("--inner-prec", default="fp32", choices=["fp32", "fp16", "bf16"])
-    args = ap.parse_args(argv)
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    if root not in sys.path:
-        sys.path.insert(0, root)
-    import paper_1111_5059_amd as dwf
-    import synth
-    ctx = dwf.Context()
-    dims = tuple(args.dims)
-    lat = dwf.Lattice(ctx, dims, args.Ls, M5=1.8, mass=args.mass)
-    U64 = lat.pack_gauge(synth.random_links(dims, args.eps, synth.link_seed(args.seed)))
-    b = lat.pack(synth.gaussian_spinor(dims, args.Ls, synth.source_seed(args.seed)))
-    x = lat.zeros(dwf.KIND_FULL)
-    ref = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.FP32), U64, b, x, tol=1e-10)
-    print(f"zero-start DWF CG: {ref['iters']} iterations", file=sys.stderr, flush=True)
-    L = args.Ls
-    inners = [(L // 2, 1.5, 0.5), (3 * L // 8, 1.5, 0.5), (L // 2, 1.0, 0.0)]
-    tols = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 1e-6]
-    rows = []
-    for inner in inners:
-        rows += scan(lat, U64, b, [inner], tols, prec_inner=dwf.PREC_NAMES[args.inner_prec])
-        for r in rows[-len(tols):]:
-            print(f"L'={r['Lp']} b={r['b']} c={r['c']} tol={r['tol_mobius']:.0e}: Moebius CG {r['mobius_iters']}, "
-                  f"guess resid {r['guess_resid']:.2e}, DWF CG after {r['dwf_iters_after']}", file=sys.stderr, flush=True)
-    print(json.dumps({"dims": dims, "Ls": L, "mass": args.mass, "eps": args.eps, "inner_prec": args.inner_prec,
-                      "zero_start_dwf_iters": ref["iters"], "rows": rows}))
-
-
-if __name__ == "__main__":
-    main()

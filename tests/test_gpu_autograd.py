@@ -51,3 +51,56 @@ def test_directional_derivative_moebius(env, ora):
     Sm = PseudofermionAction.apply(lat.to_device(ora.mat3_exp(-h * X) @ U0), phi, lat, 1e-14).item()
     fd = (Sp - Sm) / (2 * h)
     assert abs(fd - analytic) < 1e-6 * abs(analytic)
+
+
+def test_force_gradient_step_through_autograd(env, ora):
+    """tau_fg > 0: the Function returns S at U' = exp(-tau^2/24 F) U and the gradient at U'
+    (Sec. 2, the force-gradient step), with the solve at U' started from the one at U; both
+    against the oracle's force-gradient step."""
+    import torch
+    from paper_1111_5059_amd.autograd import PseudofermionAction
+    dwf, ctx = env
+    dims, Ls, tau = (4, 4, 2, 4), 6, 0.1
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8, mass=0.05)
+    U0 = synth.random_links(dims, 0.5, 1721)
+    phi_nat = synth.gaussian_spinor_parity(dims, Ls, 1722, 1)
+    phi = lat.pack(phi_nat, dwf.KIND_ODD)
+    U = lat.to_device(U0).requires_grad_(True)
+    S = PseudofermionAction.apply(U, phi, lat, 1e-13, tau)
+    info = PseudofermionAction.last_info
+    S.backward()
+    G = U.grad.cpu().numpy()
+    po = ora.params(dims, Ls, M5=1.8, mass=0.05)
+    Fp, _, (S0, S1), _ = ora.fg_force(po, U0, phi_nat, tau, tol=1e-14)
+    assert abs(S.item() - S1) < 1e-11 * abs(S1)
+    # U' from the oracle's force at U
+    _, X, _ = ora.action(po, U0, phi_nat, tol=1e-14)
+    F1, _ = ora.force(po, U0, X)
+    Up = ora.mat3_exp(-tau * tau / 24.0 * F1) @ U0
+    T = ora.generators()
+    e_from_G = np.einsum("mtzyxji,ajk,mtzyxki->mtzyxa", np.conj(G), T, Up).real
+    e_ora = -2.0 * np.einsum("ajk,mtzyxkj->mtzyxa", T, Fp).real
+    assert np.max(np.abs(e_from_G - e_ora)) < 1e-9 * np.max(np.abs(e_ora))
+    assert info["iters"] - info["iters_first"] < info["iters_first"]
+
+
+def test_unconverged_force_solve_is_reported(env):
+    """A force solve cut off at maxit returns not-converged with its true residual (the force
+    and the action are still written); the autograd Function refuses such a solve."""
+    import torch
+    from paper_1111_5059_amd.autograd import PseudofermionAction
+    dwf, ctx = env
+    dims, Ls = (4, 4, 2, 4), 6
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8, mass=0.01)
+    Ud = lat.to_device(synth.random_links(dims, 0.5, 1731))
+    phi = lat.pack(synth.gaussian_spinor_parity(dims, Ls, 1732, 1), dwf.KIND_ODD)
+    F = torch.zeros_like(Ud)
+    info = dwf.fermion_force(ctx, lat.params(), Ud, phi, F, tol=1e-12, maxit=3)
+    assert not info["converged"] and info["iters"] <= 3 and info["true_rel_resid"] > 1e-12
+    assert float(F.abs().max()) > 0.0 and info["S"] != 0.0
+    info = dwf.fermion_force(ctx, lat.params(), Ud, phi, F, tol=1e-12)
+    assert info["converged"] and info["true_rel_resid"] <= 1e-12
+    info = dwf.fermion_force(ctx, lat.params(), Ud, phi, F, tau_fg=0.1, tol=1e-12, maxit=20)
+    assert not info["converged"] and info["iters"] <= 20
+    with pytest.raises(dwf.DwfError):
+        PseudofermionAction.apply(Ud, phi, lat, 1e-12, 0.0, 3)

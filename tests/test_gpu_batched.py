@@ -106,3 +106,24 @@ def test_batch_validation(env):
         dwf.cg_ne_batched(ctx, [lat.params(), lat.params(M5=1.5)], Ug, [b, b], [x, lat.zeros(dwf.KIND_FULL)])
     with pytest.raises(dwf.DwfError):  # the same solution field twice
         dwf.cg_ne_batched(ctx, [lat.params(), lat.params()], Ug, [b, b], [x, x])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_respects_maxit(env, prec):
+    """The iteration cap holds per right-hand side over all restarts of the normal-equation
+    tolerance: no right-hand side runs more than maxit iterations."""
+    dwf, ctx = env
+    dims, Ls = (4, 4, 4, 4), 8
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8)
+    Ug = lat.pack_gauge(synth.random_links(dims, 0.4, 1621))
+    masses = [0.01, 0.3]
+    bs = [lat.pack(synth.gaussian_spinor(dims, Ls, 1622 + k)) for k in range(2)]
+    xs = [lat.zeros(dwf.KIND_FULL) for _ in range(2)]
+    pars = [lat.params(mass=m, prec_inner=dwf.PREC_NAMES[prec]) for m in masses]
+    for maxit in (7, 40):
+        infos = dwf.cg_ne_batched(ctx, pars, Ug, bs, xs, tol=1e-12, maxit=maxit)
+        for info in infos:
+            assert info["iters"] <= maxit, (maxit, info)
+        assert not infos[0]["converged"]
+        for x in xs:
+            x.zero_()

@@ -38,3 +38,30 @@ def test_scan_turning_point():
     # short inner: saturated guess, 100x more Moebius accuracy gains less than 2x in the guess
     assert short[-1]["guess_resid"] > 1e-3
     assert short[-1]["guess_resid"] > 0.5 * short[1]["guess_resid"]
+
+
+def test_scan_rows_match_the_oracle(ora):
+    """Every row of the scan (one defect-correction step at a given Moebius tolerance, FP64
+    solves) against the oracle's MADWF with n_dc = 1 at the same tolerances on the same lattice:
+    the guess residual to within a factor 1.5 and the DWF iterations after the guess to within
+    15 % (the two start the second PV solve from different guesses and tighten the final
+    normal-equation tolerance by slightly different rules)."""
+    dwf, ctx = gpu_ctx()
+    from paper_1111_5059_amd import madwf_scan
+    dims, Ls, m = (4, 4, 4, 8), 8, 0.05
+    U = synth.random_links(dims, 0.3, 1500)
+    src = synth.gaussian_spinor(dims, Ls, 1501)
+    lat = dwf.Lattice(ctx, dims, Ls, mass=m)
+    U64, b = lat.pack_gauge(U), lat.pack(src)
+    tols = [1e-1, 1e-3, 1e-5]
+    inners = [(4, 1.5, 0.5), (Ls, 1.0, 0.0)]
+    rows = madwf_scan.scan(lat, U64, b, inners, tols, tol_pv=1e-8, prec_inner=dwf.FP64, prec_final=dwf.FP64)
+    pt = ora.params(dims, Ls, M5=1.8, mass=m)
+    for r in rows:
+        pi = ora.params(dims, r["Lp"], M5=1.8, mass=m, b=r["b"], c=r["c"])
+        _, o = ora.madwf(pt, pi, U, src, n_dc=1, tol_pv=1e-8, tol_mob=r["tol_mobius"], tol=1e-10)
+        print(r, o["resid_after_dc"][0], o["final_iters"])
+        assert r["converged"] and o["converged"]
+        ratio = r["guess_resid"] / o["resid_after_dc"][0]
+        assert 1 / 1.5 < ratio < 1.5, (r, o)
+        assert abs(r["dwf_iters_after"] - o["final_iters"]) <= 0.15 * o["final_iters"] + 2, (r, o)

@@ -148,6 +148,33 @@ def test_adjoint_identities(ora, bc):
         assert abs(lhs - rhs) < 1e-12 * max(abs(lhs), 1.0)
 
 
+@pytest.mark.parametrize("dagger", [False, True])
+def test_hop5_sample_is_the_whole_lattice_hop(ora, dagger):
+    """The sampled hop (the reference of the full-size parity test) equals the whole-lattice hop at
+    every sampled (4D site, s) of both parities, and every slice of the whole-lattice hop is the
+    hopping term of the pinned 4D Wilson operator, H = 2 ((4 - M5) - D_W).  All extents and Ls
+    differ, so that a transposed or mis-strided (site, s) mapping fails."""
+    dims, Ls, M5 = (4, 6, 2, 8), 5, 1.8
+    p = ora.params(dims, Ls, M5=M5, tbc=1)
+    p4 = ora.params(dims, 1, M5=M5, tbc=1)
+    U = synth.random_links(dims, 0.6, 51)
+    psi = synth.gaussian_spinor(dims, Ls, 52)
+    V = int(np.prod(dims))
+    whole = ora.hop5(p, U, psi, dagger=dagger)
+    for s in range(Ls):
+        h = 2.0 * ((4.0 - M5) * psi[s] - ora.dw4(p4, U, psi[s], dagger=dagger))
+        assert np.max(np.abs(whole[s] - h)) < 1e-13 * np.max(np.abs(h))
+    rng = np.random.default_rng(53)
+    n = 400
+    sites = rng.integers(0, V, n)
+    svals = rng.integers(0, Ls, n)
+    got = ora.hop5_sample(p, U, psi, sites, svals, dagger=dagger)
+    ref = whole.reshape(Ls, V, 4, 3)[svals, sites]
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    par = synth.parity_array(dims).ravel()[sites]
+    assert 0 < par.sum() < n  # both output parities sampled
+
+
 def reflect5(psi):
     return psi[::-1].copy()
 
