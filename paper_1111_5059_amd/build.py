@@ -37,23 +37,39 @@ def sources():
     return units
 
 
-def _compile(unit):
+def _up_to_date(obj):
+    """The object exists and is newer than every file its dependency list (-MMD) names."""
+    dep = obj + ".d"
+    if not (os.path.exists(obj) and os.path.exists(dep)):
+        return False
+    with open(dep) as fh:
+        text = fh.read().replace("\\\n", " ")
+    files = text.split(":", 1)[1].split() if ":" in text else []
+    t = os.path.getmtime(obj)
+    return bool(files) and all(os.path.exists(f) and os.path.getmtime(f) < t for f in files)
+
+
+def _compile(unit, incremental=False):
     src, define = unit
     tag = "" if define is None else "." + define.split("=")[1]
     obj = os.path.join(OBJ, src + tag + ".o")
+    if incremental and _up_to_date(obj):
+        return src, obj, 0, ""
     extra = [] if define is None else [define]
-    cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + extra + ["-MMD", "-MF", obj + ".d", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, obj, r.returncode, r.stdout + r.stderr
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, incremental=False):
+    """Compile every translation unit and link libdwf.so.  incremental=True (development only)
+    skips units whose object is newer than every file it depends on."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     objs = []
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for src, obj, rc, out in ex.map(_compile, srcs):
+        for src, obj, rc, out in ex.map(lambda u: _compile(u, incremental), srcs):
             if rc != 0:
                 sys.stderr.write(out)
                 raise RuntimeError(f"hipcc failed on {src}")
@@ -71,4 +87,4 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))
