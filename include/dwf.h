@@ -156,6 +156,19 @@ int dwf_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in,
 int mobius_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op,
                   int parity, int dagger);
 
+/* dwf_dslash for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  Same operator, arguments, layouts
+ * and errors as dwf_dslash, but the call performs no device allocation: the neighbour tables
+ * and the intermediate half fields of M_prec live in one device array of 256 MiB per device,
+ * set up by dwf_ctx_create on the context's device (which must be current).  The call returns
+ * DWF_ERR_ARG, before any device work, when the op needs more than that (2 * V/2 * 8 index
+ * words, plus one intermediate half field for M_prec and two for M_prec^+), or when it needs a
+ * fifth-dimension block and Ls is not 8, 16 or 32 (the blocks run in recurrence form only).
+ * Every call rebuilds what it reads from the array, so no state carries over between calls;
+ * calls that overlap on one device (several streams or threads) share the array and race. */
+int dwf_dslash_noalloc(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op,
+                       int parity, int dagger);
+
 /* Solve D(m) x = b (Sec. 4, the Dirac equation) for packed FP64 full fields by
  * CG on the even-odd normal equations.  U: packed FP64 gauge.  x holds the
  * initial guess on entry.  p->prec_inner < FP64 runs the iterations in that

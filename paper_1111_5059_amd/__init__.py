@@ -91,6 +91,7 @@ SIGNATURES = {
     "dwf_convert": ([_vp, _PP, _ci, _ci, _vp, _ci, _vp], _ci),
     "dwf_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
     "mobius_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
+    "dwf_dslash_noalloc": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
     "cg_ne": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)], _ci),
     "cg_ne_batched": ([_vp, _ci, _PP, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                        ctypes.POINTER(SolveInfo)], _ci),
@@ -210,6 +211,12 @@ def dwf_dslash(ctx, p, U, src, dst, op, parity=0, dagger=False):
 def mobius_dslash(ctx, p, U, src, dst, op, parity=0, dagger=False):
     _check(lib().mobius_dslash(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(src)), _vp(_ptr(dst)),
                                int(op), int(parity), int(bool(dagger))))
+
+
+def dwf_dslash_noalloc(ctx, p, U, src, dst, op, parity=0, dagger=False):
+    """dwf_dslash without device allocation (the library's fixed per-device scratch array)."""
+    _check(lib().dwf_dslash_noalloc(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(src)), _vp(_ptr(dst)),
+                                    int(op), int(parity), int(bool(dagger))))
 
 
 def cg_ne(ctx, p, U, b, x, tol=1e-10, delta=0.1, maxit=100000):

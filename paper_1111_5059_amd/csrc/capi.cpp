@@ -187,6 +187,7 @@ int dwf_ctx_create(dwf_ctx** out, void* stream) {
     auto* c = new dwf_ctx();
     c->stream = reinterpret_cast<hipStream_t>(stream);
     DWF_CHECK_HIP(hipGetDevice(&c->device));
+    scratch_init();  // device address of the no-allocation entry point's array on this device
     DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_scalars), S_COUNT * sizeof(double)));
     *out = c;
     return DWF_OK;
@@ -315,6 +316,23 @@ int dwf_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in,
 int mobius_dslash(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op, int parity,
                   int dagger) {
   return dslash_any(ctx, p, U, in, out, op, parity, dagger, true);
+}
+
+int dwf_dslash_noalloc(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op,
+                       int parity, int dagger) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!U || !in || !out) return fail(DWF_ERR_ARG, "NULL field pointer");
+  if (in == out) return fail(DWF_ERR_ARG, "in and out must not alias");
+  if (parity != 0 && parity != 1) return fail(DWF_ERR_ARG, "parity must be 0 or 1");
+  if (op < DWF_OP_HOP || op > DWF_OP_AINV) return fail(DWF_ERR_ARG, "unknown op");
+  dwf_params q = *p;  // the Shamir operator, as dwf_dslash
+  q.b = 1.0;
+  q.c = 0.0;
+  q.b_s = nullptr;
+  q.c_s = nullptr;
+  return guarded([&]() { return dslash_noalloc(ctx, q, U, in, out, op, parity, dagger); });
 }
 
 int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info) {

@@ -623,10 +623,11 @@ static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t s
 }
 
 // epilogue: 0 none, 1 dense matrices in LDS, 2 recurrence (scan) form, 3 scan form and a
-// second, scanned output (only where the site's Ls slices form one wave segment)
+// second, scanned output (only where the site's Ls slices form one wave segment).  An epilogue
+// is given by its matrices E, by its recurrence form (epi_scan) or both; the dense form needs E.
 template <typename P, int LS, int NS, bool DAG, bool PRO, bool CG>
 static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
-  if (!a.E) return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st);
+  if (!a.E && !a.epi_scan) return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st);
   if constexpr (NS == 1 && (LS == 8 || LS == 16 || LS == 32)) {
     if (a.epi_scan) {
       if constexpr (!DAG && !CG) {
@@ -635,6 +636,7 @@ static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t
       return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 2, CG>(a, cfg, st);
     }
   }
+  if (!a.E) return -1;  // the recurrence form does not apply to this launch shape
   return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 1, CG>(a, cfg, st);
 }
 
@@ -672,6 +674,7 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
   const int threads = cfg.spb * (a.Ls / cfg.ns);
   if (threads > 256) return -1;
   if (hop_lds_bytes<P>(cfg, a.Ls, a.E != nullptr) > 65536) return -1;
+  if (a.epi_scan && !a.E && !(cfg.ns == 1 && (a.Ls == 8 || a.Ls == 16 || a.Ls == 32))) return -1;
   if (a.nsites <= 0) return 0;
   // common extents get a compile-time Ls; the others run the generic kernel
   switch (a.Ls) {

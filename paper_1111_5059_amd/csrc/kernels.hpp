@@ -40,7 +40,7 @@ struct HopArgs {
   const typename P::R* pcs = nullptr;  // each; nullptr: the constants pb, pc)
   const typename P::R* E;      // epilogue [2][Ls][Ls] or nullptr
   FifthScan<typename P::R> es; // the same epilogue in recurrence form
-  int epi_scan;                // es is valid (used when the site's lanes form a wave segment)
+  int epi_scan = 0;            // es is valid (used when the site's lanes form a wave segment)
   CHalf<P> x;                  // axpy operand (data == nullptr: none)
   typename P::R ax;
   double* norm_partials;       // per-block sum |out|^2 (|cg_r|^2 with the fused CG step) or nullptr

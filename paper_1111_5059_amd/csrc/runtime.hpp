@@ -98,6 +98,14 @@ struct dwf_ctx {
 namespace dwf {
 
 void* ws_get(dwf_ctx* ctx, const std::string& name, size_t bytes);
+
+// The no-allocation operator (dwf_dslash_noalloc): a device array of this size per device holds
+// its neighbour tables and intermediates.  scratch_init takes the array's device address on the
+// current device (once per device; called when a context is created).
+#define NOALLOC_SCRATCH_BYTES (size_t(256) << 20)
+void* scratch_init();
+int dslash_noalloc(dwf_ctx* ctx, const dwf_params& p, const void* U, const void* in, void* out, int op, int parity,
+                   int dagger);
 const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc);
 // traversal tile of the hop kernels on one lattice (0, 0, 0: the default)
 void set_tile(dwf_ctx* ctx, const int dims[4], int tbc, const int tile[3]);
