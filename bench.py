@@ -8,6 +8,9 @@ the timed steps the script measures, on the same GPU and stream:
   * the plain FP64 CG-NE solve of the same system (the comparison the metric names);
   * the Wilson hop kernel alone over the same half lattice (GB/s of algorithmic
     bytes, HIP events around back-to-back launches), the roofline object;
+  * plain CG-NE of the same system in FP16 and FP32 storage (precision alone, no MADWF);
+  * the 16^3 x 32, Ls = 16 solver (FP32 with FP64 reliable updates vs FP64) and force
+    (force kernel bandwidth, force-gradient step) configurations;
   * the FP64 CPU oracle on the host cores (bounded sample, extrapolated).
 
 python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3|cfg2|cfg1]
@@ -300,35 +303,162 @@ def sdep_measure(dwf, ctx, lat, U64, prec="fp16", reps=10):
     return out
 
 
-def cpu_baseline(workload, U, b_nat, fp64_iters, seconds_budget=25.0):
-    """FP64 oracle on the host cores: time M_prec^dag M_prec on the same operator,
-    restricted to a bounded sample (one or more applications on the workload's lattice
-    with Ls reduced so that one application fits the budget), scaled to the full Ls and
-    to the iteration count the plain FP64 GPU CG needed."""
+def cpu_baseline(workload, U, fp64_iters, seconds_budget=25.0):
+    """FP64 oracle on the host cores, timed on a bounded sample of the workload: its
+    M_prec^dag M_prec at the workload's full Ls on a slab of the lattice (the same spatial
+    extent, T = 4; the oracle's cost per site does not depend on the volume, and its dense
+    (4 Ls)^2 fifth-dimension blocks make it grow faster than linearly in Ls, so Ls is not
+    reduced), scaled by the volume ratio and by the iteration count of the plain FP64 GPU solve.
+    Beside it, one oracle CGNR solve of the 4^4, Ls = 8 system to a true residual of 1e-10,
+    timed whole."""
     import oracle
-    dims, L = workload[0], workload[1]
+    import synth
+    dims, L, mass = workload[0], workload[1], workload[2]
     nthreads = oracle.num_threads()
-    # sample: Ls_s slices of the same 4D lattice (cost is linear in Ls for the hop, the
-    # dominant term); two M^dag M applications timed
-    Ls_s = 2
-    p = oracle.params(dims, Ls_s, M5=1.8, mass=workload[2])
-    psi = np.ascontiguousarray(b_nat[:Ls_s])
-    psi = oracle.parity_mask(p, psi, 1)
+    slab = (dims[0], dims[1], dims[2], 4)
+    p = oracle.params(slab, L, M5=1.8, mass=mass)
+    Us = np.ascontiguousarray(U[:, :4])  # the links of the first four time slices
+    psi = oracle.parity_mask(p, synth.gaussian_spinor(slab, L, synth.source_seed(3, 9)), 1)
     t0 = time.perf_counter()
     reps = 0
     while True:
-        q = oracle.mprec(p, U, psi)
-        oracle.mprec(p, U, q, dagger=True)
+        q = oracle.mprec(p, Us, psi)
+        oracle.mprec(p, Us, q, dagger=True)
         reps += 1
-        if time.perf_counter() - t0 > seconds_budget or reps >= 3:
+        if time.perf_counter() - t0 > 0.5 * seconds_budget or reps >= 2:
             break
     dt = (time.perf_counter() - t0) / reps
-    per_iter_full = dt * L / Ls_s
+    vol_ratio = dims[3] / slab[3]
+    per_iter_full = dt * vol_ratio
+    # cfg1, timed directly
+    d1 = (4, 4, 4, 4)
+    U1 = synth.random_links(d1, 0.3, synth.link_seed(1))
+    b1 = synth.gaussian_spinor(d1, 8, synth.source_seed(1))
+    t1 = time.perf_counter()
+    _, info1 = oracle.solve(oracle.params(d1, 8, M5=1.8, mass=0.01), U1, b1, tol=1e-10)
+    cfg1_s = time.perf_counter() - t1
     return {"value": per_iter_full * fp64_iters, "unit": "s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{reps} x M_prec^dag M_prec of the FP64 oracle on the {dims} lattice at Ls={Ls_s} "
-                      f"({dt:.2f} s each), scaled by Ls {L}/{Ls_s} and by the {fp64_iters} CG iterations of "
-                      f"the plain FP64 GPU solve (extrapolated time-to-solution of the oracle's CGNR)",
-            "seconds_per_iteration": per_iter_full}
+            "sample": f"{reps} x M_prec^dag M_prec of the FP64 oracle at Ls={L} on a {slab} slab of the "
+                      f"{dims} lattice ({dt:.2f} s each), scaled by the volume ratio {vol_ratio:g} and by the "
+                      f"{fp64_iters} CG iterations of the plain FP64 GPU solve (extrapolated time-to-solution "
+                      f"of the oracle's CGNR)",
+            "seconds_per_iteration": per_iter_full,
+            "cfg1_direct": {"workload": "Shamir DWF 4^4 Ls=8 M5=1.8 mf=0.01, eps=0.3 links, CGNR to a true "
+                                        "residual 1e-10, timed whole", "seconds": cfg1_s,
+                            "iters": info1["iters"], "true_rel_resid": info1["true_rel_resid"]}}
+
+
+def precision_controls(dwf, ctx, lat, U64, bg, precs=("fp16", "fp32")):
+    """Plain CG-NE on the headline system in FP16 and FP32 storage (FP32 arithmetic, FP64
+    reliable updates, FP64 solution), no Moebius acceleration, to the same 1e-10 true residual:
+    what the precision alone buys, beside what MADWF buys (Table 1, Sec. 5)."""
+    import torch
+    out = {}
+    for prec in precs:
+        x = lat.zeros(dwf.KIND_FULL)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10)
+        torch.cuda.synchronize()
+        out[prec] = dict(info, wall_s=time.perf_counter() - t)
+        log(f"plain {prec} CG: {out[prec]['wall_s']:.2f} s, {info['iters']} iterations, "
+            f"{info['reliable_updates']} reliable updates, resid {info['true_rel_resid']:.2e}")
+        del x
+    return out
+
+
+def cfg2_measure(dwf):
+    """Shamir DWF 16^3 x 32, Ls = 16, m = 0.01, eps = 0.5: FP32 iterations with FP64 reliable
+    updates against plain FP64 CG-NE, both to a true residual of 1e-10, and the Wilson hop
+    alone in FP64 / FP32 / FP16 (its fields, 25-100 MB, partly fit the 256 MB last-level cache)."""
+    import torch
+    import synth
+    dims, Ls = (16, 16, 16, 32), 16
+    ctx = dwf.Context()
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8, mass=0.01)
+    U64 = lat.pack_gauge(synth.random_links(dims, 0.5, synth.link_seed(2)))
+    bg = lat.pack(synth.gaussian_spinor(dims, Ls, synth.source_seed(2)))
+    dwf.cg_ne(ctx, lat.params(prec_inner=dwf.FP32), U64, bg, lat.zeros(dwf.KIND_FULL), tol=1e-10, maxit=3)
+    solves = {}
+    for prec in ("fp64", "fp32"):
+        x = lat.zeros(dwf.KIND_FULL)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10)
+        torch.cuda.synchronize()
+        solves[prec] = dict(info, wall_s=time.perf_counter() - t)
+        log(f"cfg2 {prec} CG: {solves[prec]['wall_s']:.3f} s, {info['iters']} iterations")
+    hop = {prec: time_hop(dwf, ctx, lat, U64, prec, reps=50) for prec in ("fp64", "fp32", "fp16")}
+    for prec, h in hop.items():
+        log(f"cfg2 hop {prec}: {h['ms']:.4f} ms, {h['GBps']:.0f} GB/s")
+    ctx.close()
+    torch.cuda.empty_cache()
+    return {"workload": "Shamir DWF 16^3x32 Ls=16 M5=1.8 mf=0.01, random SU(3) links eps=0.5, Gaussian source, "
+                        "true residual 1e-10",
+            "fp64_cg": solves["fp64"], "fp32_reliable_cg": solves["fp32"],
+            "speedup_fp32_over_fp64": solves["fp64"]["wall_s"] / solves["fp32"]["wall_s"],
+            "dslash": {k: {"GBps": v["GBps"], "pct_hbm_peak": 100 * v["GBps"] / HBM_PEAK_GBS, "GFLOPs": v["GFLOPs"],
+                           "ms": v["ms"]} for k, v in hop.items()}}
+
+
+def cfg4_measure(dwf, tau=0.1):
+    """Fermion force (Sec. 2) of S = phi^dag (M_prec^dag M_prec)^-1 phi on 16^3 x 32, Ls = 16,
+    m = 0.01 (eps = 0.5 links, Gaussian phi on odd sites), FP64 solve to 1e-10: the call's time, the
+    force kernel's time and bandwidth (library timer, algorithmic bytes: the four FP64 half fields
+    it contracts, the links and the force once), and the force-gradient step at tau = 0.1 with its
+    second solve started from the first (iterations at U and at U')."""
+    import torch
+    import synth
+    dims, Ls = (16, 16, 16, 32), 16
+    ctx = dwf.Context()
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8, mass=0.01)
+    U = synth.random_links(dims, 0.5, synth.link_seed(4))
+    Ud = lat.to_device(U)
+    phi = lat.pack(synth.gaussian_spinor_parity(dims, Ls, synth.source_seed(4), 1), dwf.KIND_ODD)
+    # the force-gradient step with the heatbath pseudofermion phi = M^dag eta (a Gaussian phi
+    # gives forces of O(100) per generator, which move U' far from U)
+    eta = lat.pack(synth.gaussian_spinor_parity(dims, Ls, synth.source_seed(4, 1), 1), dwf.KIND_ODD)
+    phi_hb = lat.empty(dwf.KIND_ODD)
+    dwf.dwf_dslash(ctx, lat.params(), lat.pack_gauge(U), eta, phi_hb, dwf.OP_MPREC, 1, True)
+    F = torch.zeros_like(Ud)
+    dwf.fermion_force(ctx, lat.params(), Ud, phi, F, tol=1e-10, maxit=5)  # allocations
+    torch.cuda.synchronize()
+    dwf.dwf_timing_report(ctx)
+    dwf.dwf_timing_enable(ctx, True)
+    t = time.perf_counter()
+    info = dwf.fermion_force(ctx, lat.params(), Ud, phi, F, tol=1e-10)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t
+    rep = dwf.dwf_timing_report(ctx)
+    dwf.dwf_timing_enable(ctx, False)
+    fk = rep.get("force_kernel")
+    F1 = torch.zeros_like(Ud)
+    dwf.fermion_force(ctx, lat.params(), Ud, phi_hb, F1, tol=1e-10)
+    t = time.perf_counter()
+    fg = dwf.fermion_force(ctx, lat.params(), Ud, phi_hb, F, tau_fg=tau, x_io=lat.zeros(dwf.KIND_ODD), tol=1e-10)
+    torch.cuda.synchronize()
+    fg_secs = time.perf_counter() - t
+    # the solve at U' = exp(-tau^2/24 F1) U from zero, for comparison
+    Up = torch.matrix_exp(-(tau * tau / 24.0) * F1.reshape(-1, 3, 3)) @ Ud.reshape(-1, 3, 3)
+    zero = dwf.fermion_force(ctx, lat.params(), Up.reshape(Ud.shape).contiguous(), phi_hb, F, tol=1e-10)
+    del Up, F1
+    ctx.close()
+    torch.cuda.empty_cache()
+    out = {"workload": "fermion force, Shamir DWF 16^3x32 Ls=16 M5=1.8 mf=0.01, random SU(3) links eps=0.5, Gaussian "
+                       "phi on odd sites, FP64 solve to a normal-equation residual of 1e-10",
+           "seconds": secs, "iters": info["iters"], "converged": info["converged"],
+           "force_kernel": None,
+           "fg_step": {"tau": tau, "phi": "M^dag eta, eta Gaussian on odd sites", "seconds": fg_secs,
+                       "iters_first": fg["iters_first"], "iters_forecast": fg["iters"] - fg["iters_first"],
+                       "iters_at_Uprime_from_zero": zero["iters"], "converged": fg["converged"]}}
+    if fk:
+        ms = fk["ms"] / fk["launches"]
+        out["force_kernel"] = {"avg_ms": ms, "bytes_per_launch": fk["bytes"] / fk["launches"],
+                               "GBps": fk["bytes"] / fk["launches"] / (ms * 1e-3) / 1e9}
+        log(f"cfg4 force kernel: {ms:.3f} ms, {out['force_kernel']['GBps']:.0f} GB/s")
+    log(f"cfg4 force: {secs:.2f} s ({info['iters']} iterations); FG step: {fg['iters_first']} + "
+        f"{fg['iters'] - fg['iters_first']} iterations (from zero at U': {zero['iters']})")
+    return out
 
 
 def madwf_scan_run(dwf, dims=(32, 32, 32, 8), Ls=32, mass=0.005, eps=0.6, seed=6, inner_prec="fp32"):
@@ -503,11 +633,21 @@ def main():
         log(f"Moebius M^dag M (fp16): constant coefficients {sdep['constant_ms']:.2f} ms, s-dependent "
             f"{sdep['s_dependent_ms']:.2f} ms")
 
+    controls = None
+    if not args.no_extras:
+        controls = precision_controls(dwf, ctx, lat, U64, bg)
+
+    cfg2 = cfg4 = None
+    if not args.no_extras and args.workload == "cfg3":
+        cfg2 = cfg2_measure(dwf)
+        cfg4 = cfg4_measure(dwf)
+
     cpu = None
     if not args.no_cpu_baseline and fp64 is not None:
         log("CPU oracle baseline ...")
-        cpu = cpu_baseline(WORKLOADS[args.workload], U, b_nat, fp64["iters"])
-        log(f"oracle: {cpu['seconds_per_iteration']:.2f} s per CG iteration on {cpu['cores']} threads")
+        cpu = cpu_baseline(WORKLOADS[args.workload], U, fp64["iters"])
+        log(f"oracle: {cpu['seconds_per_iteration']:.2f} s per CG iteration on {cpu['cores']} threads; cfg1 solve "
+            f"{cpu['cfg1_direct']['seconds']:.2f} s")
 
     roof = None
     if dom is not None:
@@ -541,6 +681,9 @@ def main():
         "madwf": last,
         "fp64_cg": fp64,
         "speedup_vs_fp64_cg": (fp64["wall_s"] / sec) if fp64 else None,
+        "precision_only_cg": controls,
+        "speedup_vs_fp16_cg": (controls["fp16"]["wall_s"] / sec) if controls else None,
+        "speedup_vs_fp32_cg": (controls["fp32"]["wall_s"] / sec) if controls else None,
         "wilson_apps_ratio_fp64_over_madwf": (fp64["wilson_apps"] / last["wilson_apps"]) if fp64 and last else None,
         "dslash": {k: {"GBps": v["GBps"], "pct_hbm_peak": 100 * v["GBps"] / HBM_PEAK_GBS, "GFLOPs": v["GFLOPs"],
                        "ms": v["ms"]} for k, v in hop.items()},
@@ -549,6 +692,8 @@ def main():
                                 "GBps": v["bytes"] / (v["ms"] * 1e6), "share_of_step": v["ms"] * 1e-3 / elapsed}
                             for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["ms"])},
         "cpu_baseline": cpu,
+        "cfg2_solver": cfg2,
+        "cfg4_force": cfg4,
         "hasenbusch_ladder": ladder,
         "fgi_trajectory": fgi,
         "s_dependent_moebius": sdep,

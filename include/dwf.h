@@ -291,8 +291,8 @@ int dwf_tune_tile(dwf_ctx* ctx, const int* dims, int tbc, const int* tile);
 int dwf_tune_tile_get(dwf_ctx* ctx, const int* dims, int tbc, int* tile);
 
 /* Measurement.  dwf_timing_enable(ctx, 1) starts recording a HIP event pair on the
- * context stream around every Wilson-hop and fifth-dimension kernel launch the
- * context makes (the events add a few microseconds between launches);
+ * context stream around every Wilson-hop, fifth-dimension and fermion-force kernel
+ * launch the context makes (the events add a few microseconds between launches);
  * dwf_timing_enable(ctx, 0) stops recording and discards the records.
  * dwf_timing_report synchronizes the context stream and writes one line per
  * kernel variant launched since the last report,

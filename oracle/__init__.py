@@ -82,6 +82,7 @@ def lib():
             "ora_madwf": ([P, P, vp, vp, vp, ci, cd, cd, cd, ci, ctypes.POINTER(MadwfInfo)], ci),
             "ora_action": ([P, vp, vp, vp, cd, ci, ctypes.POINTER(ci)], cd),
             "ora_force": ([P, vp, vp, vp, vp], None),
+            "ora_force_sample": ([P, vp, vp, ctypes.c_long, vp, vp, vp, vp], None),
             "ora_gauge_action": ([P, vp, cd], cd),
             "ora_gauge_force": ([P, vp, cd, vp], None),
             "ora_fgi_trajectory": ([P, cd, cd, ci, vp, vp, vp, cd, ci, ctypes.POINTER(cd), ctypes.POINTER(ci)], None),
@@ -296,6 +297,20 @@ def force(p, U, X):
     lib().ora_force(ctypes.byref(p), _ptr(U), _ptr(X), _ptr(F), e.ctypes.data_as(ctypes.c_void_p))
     dims_r = tuple(int(p.dims[k]) for k in (3, 2, 1, 0))
     return F.reshape((4,) + dims_r + (3, 3)), e.reshape((4,) + dims_r + (8,))
+
+
+def force_sample(p, U, X, sites, mus):
+    """The force of force() on sampled links (lexicographic 4D index sites[k], direction mus[k]):
+    returns (F[n][3][3], e[n][8])."""
+    U, X = _c(U), _c(X)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    mus = np.ascontiguousarray(mus, dtype=np.int32)
+    n = len(sites)
+    F = np.zeros((n, 3, 3), np.complex128)
+    e = np.zeros((n, 8), np.float64)
+    lib().ora_force_sample(ctypes.byref(p), _ptr(U), _ptr(X), n, sites.ctypes.data_as(ctypes.c_void_p),
+                           mus.ctypes.data_as(ctypes.c_void_p), _ptr(F), e.ctypes.data_as(ctypes.c_void_p))
+    return F, e
 
 
 def quotient_force(pn, pd, U, phi, x0=None, tol=1e-13, maxit=100000):

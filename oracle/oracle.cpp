@@ -800,6 +800,11 @@ double ora_action(const ora_params* p, const cplx* U, const cplx* phi, cplx* X, 
   return dot(phi, X, n).real();
 }
 
+static void link_force(const Geom& g, int Ls, const cplx* U, const cplx* W, const cplx* Z, long i, int mu, cplx* Fm,
+                       double* e);
+static void force_fields(const ora_params* p, const cplx* U, const cplx* X, const cplx* Yin, std::vector<cplx>& W,
+                         std::vector<cplx>& Z);
+
 // The derivative of the bilinear form -2 Re <Y, M X> (X, Y on odd sites, M = M_prec of p)
 // along every link and generator: e_a = d/dw [-2 Re <Y, M[exp(w T_a) U_mu(x)] X>] at w = 0
 // (Sec. 2: e_a acts on the link as left multiplication by T_a).  With Y = M X this is
@@ -809,9 +814,26 @@ double ora_action(const ora_params* p, const cplx* U, const cplx* phi, cplx* X, 
 static void force_xy(const ora_params* p, const cplx* U, const cplx* X, const cplx* Yin, cplx* F, double* e_out) {
   Geom g = geom_of(p);
   const int Ls = p->Ls;
+  std::vector<cplx> W, Z;
+  force_fields(p, U, X, Yin, W, Z);
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < g.V; ++i)
+    for (int mu = 0; mu < 4; ++mu)
+      link_force(g, Ls, U, W.data(), Z.data(), i, mu, F + ((long)mu * g.V + i) * 9,
+                 e_out ? e_out + ((long)mu * g.V + i) * 8 : nullptr);
+}
+
+// The fields the force contracts: W = F (X + X_e) and Z = Y_o' + Y_e' (both parities), with
+// X_e = A^-1 B_eo X, Y_o' = A^-dag Y, Y_e' = A^-dag B_oe^dag Y_o'.
+static void force_fields(const ora_params* p, const cplx* U, const cplx* X, const cplx* Yin, std::vector<cplx>& W,
+                         std::vector<cplx>& Z) {
+  Geom g = geom_of(p);
+  const int Ls = p->Ls;
   const long V12 = g.V * 12, n = V12 * Ls;
   EOContext E(p);
-  std::vector<cplx> Y(Yin, Yin + n), Xe(n), Yo(n), Ye(n), t(n), W(n), Z(n), Xo(X, X + n);
+  std::vector<cplx> Y(Yin, Yin + n), Xe(n), Yo(n), Ye(n), t(n), Xo(X, X + n);
+  W.assign(n, cplx(0));
+  Z.assign(n, cplx(0));
   mask_parity(g, Ls, Xo.data(), 1);
   mask_parity(g, Ls, Y.data(), 1);
   apply_B(p, g, U, Xo.data(), t.data(), 0, 0);
@@ -821,17 +843,22 @@ static void force_xy(const ora_params* p, const cplx* U, const cplx* X, const cp
   apply_fifth(g, Ls, E.Ainvdag, t.data(), Ye.data());        // Y_e' = A^-dag B_oe^dag Y_o'
   for (long k = 0; k < n; ++k) { t[k] = Xo[k] + Xe[k]; Z[k] = Yo[k] + Ye[k]; }
   apply_F(p, g, t.data(), W.data(), 0);                      // W = F (X + X_e)
+}
+
+// The force on one link (x = site i, direction mu) from the fields W = F (X + X_e) and
+// Z = Y_o' + Y_e' of force_xy: Fm = sum_a e_a T_a, e (optional) = the eight e_a.
+static void link_force(const Geom& g, int Ls, const cplx* U, const cplx* W, const cplx* Z, long i, int mu, cplx* Fm,
+                       double* e) {
+  const long V12 = g.V * 12;
   const Gammas& G = gam();
   const GellMann& T = gm();
   // e_a(S) = -Re sum_s [ Z(x)^dag (1-g_mu) dU W(x+mu) + Z(x+mu)^dag (1+g_mu) dU^dag W(x) ]
   // with dU = T_a U (times the boundary phase of the link), dU^dag = -U^dag T_a.
-#pragma omp parallel for schedule(static)
-  for (long i = 0; i < g.V; ++i) {
-    for (int mu = 0; mu < 4; ++mu) {
+  {
+    {
       double ph;
       const long f = step(g, i, mu, +1, &ph);
       const cplx* Ul = link(g, U, mu, i);
-      cplx Fm[9];
       for (int k = 0; k < 9; ++k) Fm[k] = 0;
       for (int a = 0; a < 8; ++a) {
         cplx dU[9], dUd[9];
@@ -865,10 +892,9 @@ static void force_xy(const ora_params* p, const cplx* U, const cplx* X, const cp
           for (int k = 0; k < 12; ++k) acc += std::conj(Z[s * V12 + f * 12 + k]) * pv[k];
         }
         const double ea = -acc.real();
-        if (e_out) e_out[((long)mu * g.V + i) * 8 + a] = ea;
+        if (e) e[a] = ea;
         for (int k = 0; k < 9; ++k) Fm[k] += ea * T.T[a][k];
       }
-      for (int k = 0; k < 9; ++k) F[((long)mu * g.V + i) * 9 + k] = Fm[k];
     }
   }
 }
@@ -882,6 +908,22 @@ void ora_force(const ora_params* p, const cplx* U, const cplx* X, cplx* F, doubl
   mask_parity(g, p->Ls, Xo.data(), 1);
   mprec(p, E, U, Xo.data(), Y.data(), 0);
   force_xy(p, U, Xo.data(), Y.data(), F, e_out);
+}
+
+// The force of ora_force evaluated only on n sampled links (lexicographic 4D site sites[k],
+// direction mus[k]): F[n][3][3], e (optional) [n][8].  The same per-link definition.
+void ora_force_sample(const ora_params* p, const cplx* U, const cplx* X, long n, const long* sites, const int* mus,
+                      cplx* F, double* e_out) {
+  Geom g = geom_of(p);
+  const long nf = g.V * 12 * p->Ls;
+  EOContext E(p);
+  std::vector<cplx> Xo(X, X + nf), Y(nf), W, Z;
+  mask_parity(g, p->Ls, Xo.data(), 1);
+  mprec(p, E, U, Xo.data(), Y.data(), 0);
+  force_fields(p, U, Xo.data(), Y.data(), W, Z);
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < n; ++k)
+    link_force(g, p->Ls, U, W.data(), Z.data(), sites[k], mus[k], F + k * 9, e_out ? e_out + k * 8 : nullptr);
 }
 
 // Hasenbusch quotient action (Sec. 3): with a numerator mass pn->mass and a denominator mass

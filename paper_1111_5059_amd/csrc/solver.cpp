@@ -820,9 +820,14 @@ static void force_terms(dwf_ctx* ctx, const Op<P64>& op, const void* Unat, CHalf
   op.hop(0, cv(Zo), Ze, true, false, -0.5, op.em(E_AINVDAG_FDAG));      // Y_e' = A^-dag B_oe^dag Y_o'
   op.fifth(X, Wo, E_F);                                                 // W_o = F X
   op.fifth(cv(Xe), We, E_F);                                            // W_e = F X_e
+  const long mark = ctx->timer.on ? timer_begin(ctx, "force_kernel") : -1;
   DWF_CHECK_LAUNCH(launch_force(g->tables(), Ls, cv(We), cv(Wo), cv(Ze), cv(Zo),
                                 reinterpret_cast<const double2*>(Unat), g->tbc, g->dims, kind,
                                 reinterpret_cast<double2*>(Fout), ctx->stream, coef, accumulate));
+  // algorithmic bytes: the four FP64 half fields W_e, W_o, Z_e, Z_o and the links read once, the
+  // force written once (and read once when accumulating)
+  if (mark >= 0)
+    timer_end(ctx, mark, 4.0 * double(hb) + double(4 * g->V) * 9 * sizeof(double2) * (accumulate ? 3 : 2));
 }
 
 // S and the force at the links Unat.  X solves M^dag M X = phi to the normal-equation tolerance

@@ -407,6 +407,28 @@ def test_force_finite_difference(ora, bc, tbc):
     assert np.max(np.abs(np.trace(F, axis1=-2, axis2=-1))) < 1e-12
 
 
+def test_force_sample_is_the_whole_lattice_force(ora):
+    """The sampled force (the reference of the full-size force test) equals the whole-lattice
+    force on every sampled link of both parities and all four directions (all extents differ, so
+    a mis-strided (site, mu) mapping fails)."""
+    dims, Ls = (4, 6, 2, 8), 4
+    p = ora.params(dims, Ls, M5=1.8, mass=0.1, b=1.5, c=0.5, tbc=1)
+    U = synth.random_links(dims, 0.5, 81)
+    X = synth.gaussian_spinor_parity(dims, Ls, 82, 1)
+    F, e = ora.force(p, U, X)
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(83)
+    sites = rng.integers(0, V, 200)
+    mus = rng.integers(0, 4, 200)
+    Fs, es = ora.force_sample(p, U, X, sites, mus)
+    Fw = F.reshape(4, V, 3, 3)[mus, sites]
+    ew = e.reshape(4, V, 8)[mus, sites]
+    assert np.max(np.abs(Fs - Fw)) <= 1e-14 * np.max(np.abs(Fw))
+    assert np.max(np.abs(es - ew)) <= 1e-14 * np.max(np.abs(ew))
+    par = synth.parity_array(dims).ravel()[sites]
+    assert 0 < par.sum() < len(sites) and set(mus) == {0, 1, 2, 3}
+
+
 def test_force_gauge_covariance(ora):
     dims, Ls = (4, 2, 2, 4), 4
     p = ora.params(dims, Ls, M5=1.8, mass=0.05)
