@@ -5,7 +5,7 @@
 // For the link U_mu(x) only two hop terms contribute:
 //   <Z, dH W> = tr(dU Q1) + tr(dU^+ Q2),
 //   Q1 = sum_{s,spin} [(1 - g_mu) W(x+mu)] Z(x)^+,  Q2 = sum_{s,spin} [(1 + g_mu) W(x)] Z(x+mu)^+ .
-// One thread per link accumulates Q1, Q2 over s (FP64), then writes either
+// The lanes of one link accumulate Q1, Q2 over their slices s (FP64) and sum them; one writes either
 //   F = sum_a e_a T_a = -1/2 TA(Q2 U^+ - U Q1)     (T_a = i lambda_a / 2)
 // or the ambient gradient G = -(Q1^+ + Q2) (dS = Re sum conj(G) dU).
 // The force-gradient update U' = exp(-eps F) U uses the Cayley-Hamilton form of
@@ -52,21 +52,41 @@ struct ForceArgs {
   double2* F;
 };
 
-template <int MU>
-__device__ void force_link(const ForceArgs& a, int p, long x) {
-  const long xf = a.nbr[p][x * 8 + MU];
+// Lane layout: the SEG lanes of one aligned wave segment share one link and take the slices
+// s = lane, lane + SEG, ... of the fifth dimension, so that their loads of the s-fastest
+// [x_cb][12][Ls] fields are contiguous.  The partial sums of Q1 and Q2 are then added across the
+// segment by butterfly shuffles (fixed order), and the segment's first lane writes the link.
+template <int SEG>
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < SEG; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int MU, int SEG>
+__device__ void force_link(const ForceArgs& a, int p, long x, int lane, bool active) {
   C Q1[9], Q2[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Q1[k] = Q2[k] = {0.0, 0.0};
-  for (int s = 0; s < a.Ls; ++s) {
-    C w[12], z[12];
-    load_spinor<P64>(a.W[1 - p], xf, s, a.Ls, w);
-    load_spinor<P64>(a.Z[p], x, s, a.Ls, z);
-    outer_acc<MU, -1>(w, z, Q1);
-    load_spinor<P64>(a.W[p], x, s, a.Ls, w);
-    load_spinor<P64>(a.Z[1 - p], xf, s, a.Ls, z);
-    outer_acc<MU, +1>(w, z, Q2);
+  const long xf = active ? a.nbr[p][x * 8 + MU] : 0;
+  if (active) {
+    for (int s = lane; s < a.Ls; s += SEG) {
+      C w[12], z[12];
+      load_spinor<P64>(a.W[1 - p], xf, s, a.Ls, w);
+      load_spinor<P64>(a.Z[p], x, s, a.Ls, z);
+      outer_acc<MU, -1>(w, z, Q1);
+      load_spinor<P64>(a.W[p], x, s, a.Ls, w);
+      load_spinor<P64>(a.Z[1 - p], xf, s, a.Ls, z);
+      outer_acc<MU, +1>(w, z, Q2);
+    }
   }
+  // (every lane of the segment takes part in the shuffles: active is uniform over a segment)
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Q1[k] = {seg_sum<SEG>(Q1[k].re), seg_sum<SEG>(Q1[k].im)};
+    Q2[k] = {seg_sum<SEG>(Q2[k].re), seg_sum<SEG>(Q2[k].im)};
+  }
+  if (!active || lane != 0) return;
   const int code = a.linksrc[p][x * 8 + MU];
   const long l = code >> 1;
   const double ph = (code & 1) ? -1.0 : 1.0;
@@ -121,18 +141,25 @@ __device__ void force_link(const ForceArgs& a, int p, long x) {
   }
 }
 
+// SEG lanes per link (SEG a power of two, at least Ls when Ls <= 64).  One wave takes 64 / SEG
+// sites in one direction mu (so that the branch on mu is uniform over the wave); four consecutive
+// waves take the same sites in the four directions.
+template <int SEG>
 __global__ void __launch_bounds__(256) force_kernel(ForceArgs a) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * a.nsites * 4) return;
-  const int mu = int(i & 3);
-  const long j = i >> 2;
+  constexpr int SPW = 64 / SEG;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long wave = t >> 6;
+  const int mu = int(wave & 3);
+  const long j = (wave >> 2) * SPW + ((t & 63) / SEG);  // site index over both parities
+  const int lane = int(t & (SEG - 1));
+  const bool active = j < 2 * a.nsites;
   const int p = j >= a.nsites ? 1 : 0;
-  const long x = j - p * a.nsites;
+  const long x = active ? j - p * a.nsites : 0;
   switch (mu) {
-    case 0: force_link<0>(a, p, x); break;
-    case 1: force_link<1>(a, p, x); break;
-    case 2: force_link<2>(a, p, x); break;
-    default: force_link<3>(a, p, x); break;
+    case 0: force_link<0, SEG>(a, p, x, lane, active); break;
+    case 1: force_link<1, SEG>(a, p, x, lane, active); break;
+    case 2: force_link<2, SEG>(a, p, x, lane, active); break;
+    default: force_link<3, SEG>(a, p, x, lane, active); break;
   }
 }
 
@@ -153,8 +180,21 @@ int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CH
   a.coef = coef;
   a.accumulate = accumulate;
   a.F = F;
-  const long n = 2 * g.nsites * 4;
-  hipLaunchKernelGGL(force_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  // lanes per link: the smallest power of two covering Ls, at most 64; 4 waves per 64 / seg sites
+  int seg = 1;
+  while (seg < Ls && seg < 64) seg <<= 1;
+  const long spw = 64 / seg;
+  const long waves = 4 * ((2 * g.nsites + spw - 1) / spw);
+  const unsigned blocks = (unsigned)((waves * 64 + 255) / 256);
+  switch (seg) {
+    case 1: hipLaunchKernelGGL(force_kernel<1>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(force_kernel<2>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(force_kernel<4>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(force_kernel<8>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(force_kernel<16>, dim3(blocks), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(force_kernel<32>, dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL(force_kernel<64>, dim3(blocks), dim3(256), 0, st, a); break;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
