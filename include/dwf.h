@@ -270,7 +270,13 @@ int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* mass
  * LDS mode link_lds: 0 nothing staged, 1 the workgroup's links staged in LDS,
  * 2 the neighbour spinors of every direction staged in LDS (FP16, Ls 8/16/32,
  * one slice per thread, 256 / Ls sites per workgroup).  Used by the autotuner;
- * kernel_id 0 = hop.  sites_per_block = s_per_thread = 0 restores the default.
+ * kernel_id 0 = hop, 1 = the batched hop of cg_ne_batched / quotient_force on separate
+ * fields (one slice per thread, link_lds 0 or 1; xcd_remap also keeps the right-hand
+ * sides of one site block on one XCD), 2 = the batched hop on right-hand sides
+ * interleaved along the fifth dimension (Shamir, Ls 8/16/32: the batched solvers use it
+ * unless it is switched off; sites_per_block 1 = on, -1 = off, s_per_thread 1, link_lds
+ * 0 or 1; the workgroup holds the whole site, 256 / (nrhs Ls) sites).
+ * sites_per_block = s_per_thread = 0 restores the default.
  * Rejects shapes the kernel cannot run (more than 256 threads, Ls not divisible
  * by s_per_thread, LDS above 64 KiB, mode 2 outside its shape) with DWF_ERR_ARG. */
 int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int sites_per_block, int s_per_thread,

@@ -10,12 +10,17 @@ threads, LDS above 64 KiB) are never tried: the library rejects them before laun
 ``tune_tile`` searches the traversal tile of a lattice the same way (``dwf_tune_tile``): the
 3D tile of spatial sites the workgroups walk along t, which sets how much of each input
 spinor's re-reads the L2 serves.
+
+``tune_batched`` searches the batched solve (``cg_ne_batched``) over its hop's launch shapes:
+right-hand sides interleaved along the fifth dimension (kernel 2: XCD order, links in LDS) or
+on separate fields (kernel 1: sites per workgroup, XCD order, links in LDS), timing a fixed
+number of iterations of the batched CG for (precision, Ls, number of right-hand sides, lattice).
 """
 import json
 import os
 
-from . import (FP64, KIND_GAUGE, KIND_ODD, OP_MPREC, PREC_NAMES, DwfError, dwf_convert, dwf_dslash,
-               dwf_tune_get, dwf_tune_set, dwf_tune_tile, dwf_tune_tile_get)
+from . import (FP64, KIND_FULL, KIND_GAUGE, KIND_ODD, OP_MPREC, PREC_NAMES, DwfError, cg_ne_batched, dwf_convert,
+               dwf_dslash, dwf_tune_get, dwf_tune_set, dwf_tune_tile, dwf_tune_tile_get)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dwf_mi355x_tune.json")
 
@@ -166,3 +171,97 @@ def current(lattice, prec):
     P = PREC_NAMES.get(prec, prec)
     spb, ns, xcd, ll = dwf_tune_get(lattice.ctx, P, lattice.Ls)
     return {"spb": spb, "ns": ns, "xcd": xcd, "ll": ll}
+
+
+# ------------------------------------------------------------------ batched solve
+BATCH_SEPARATE, BATCH_INTERLEAVED = 1, 2  # kernel ids of the two batched hops
+
+
+def batch_candidates(prec, Ls, nrhs):
+    """Launch shapes of the batched solve: interleaved right-hand sides (Shamir, Ls 8/16/32, at
+    most 256 / Ls of them per launch) and separate fields (one slice per thread)."""
+    elem_c = 16 if prec == FP64 else 8
+    elem_s = {0: 16, 1: 8}.get(prec, 4)
+    lsite = 160 if prec == 2 else 72  # FP16 links are staged in two forms
+    out = []
+    if Ls in (8, 16, 32):
+        for ll in (0, 1):
+            for xcd in (0, 1):
+                out.append({"mode": "interleaved", "spb": 1, "xcd": xcd, "ll": ll})
+    for spb in (1, 2, 4, 8, 16, 32):
+        if spb * Ls > 256 or spb * Ls < 32:
+            continue
+        for ll in (0, 1):
+            if spb * 12 * Ls * elem_c + ll * spb * lsite * elem_s > 65536:
+                continue
+            for xcd in (0, 1):
+                out.append({"mode": "separate", "spb": spb, "xcd": xcd, "ll": ll})
+    return out
+
+
+def install_batched(ctx, prec, Ls, c):
+    """Install a batched-solve shape; c None restores the defaults."""
+    P = PREC_NAMES.get(prec, prec)
+    if c is None:
+        dwf_tune_set(ctx, P, Ls, 0, 0, kernel_id=BATCH_INTERLEAVED)
+        dwf_tune_set(ctx, P, Ls, 0, 0, kernel_id=BATCH_SEPARATE)
+        return
+    if c["mode"] == "interleaved":
+        dwf_tune_set(ctx, P, Ls, 1, 1, c["xcd"], c["ll"], kernel_id=BATCH_INTERLEAVED)
+    else:
+        dwf_tune_set(ctx, P, Ls, -1, 1, 1, 0, kernel_id=BATCH_INTERLEAVED)  # interleaving off
+        dwf_tune_set(ctx, P, Ls, c["spb"], 1, c["xcd"], c["ll"], kernel_id=BATCH_SEPARATE)
+
+
+def _batch_key(prec, Ls, nrhs, dims):
+    return f"batch|{prec}|{Ls}|{nrhs}|{'x'.join(str(d) for d in dims)}"
+
+
+def tune_batched(lattice, U64, prec, masses, iters=10, cache=DEFAULT_CACHE, shapes=None, verbose=False):
+    """Time ``iters`` iterations of the batched CG of len(masses) right-hand sides (Gaussian
+    sources, zero guesses) for every shape; installs the fastest and returns (shape, ms per
+    iteration, table)."""
+    import time
+    import torch
+    P = PREC_NAMES.get(prec, prec)
+    ctx, Ls, n = lattice.ctx, lattice.Ls, len(masses)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    b = lattice.empty(KIND_FULL)
+    b.view(torch.float64).normal_(generator=g)
+    pars = [lattice.params(mass=m, prec_inner=P) for m in masses]
+    table, best = [], None
+    for c in shapes or batch_candidates(P, Ls, n):
+        try:
+            install_batched(ctx, P, Ls, c)
+        except DwfError:
+            continue
+        xs = [lattice.zeros(KIND_FULL) for _ in range(n)]
+        cg_ne_batched(ctx, pars, U64, [b] * n, xs, tol=1e-14, maxit=2)  # allocations
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cg_ne_batched(ctx, pars, U64, [b] * n, xs, tol=1e-14, maxit=iters)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / iters
+        del xs
+        table.append(dict(c, ms=ms))
+        if verbose:
+            print(f"batch tune {prec} Ls={Ls} nrhs={n} {c}: {ms:.3f} ms per iteration", flush=True)
+        if best is None or ms < best[1]:
+            best = (c, ms)
+    install_batched(ctx, P, Ls, best[0])
+    if cache:
+        save(cache, _batch_key(P, Ls, n, lattice.dims), dict(best[0], ms=best[1]))
+    return best[0], best[1], table
+
+
+def current_batched(ctx, prec, Ls):
+    """The installed batched-solve shape."""
+    P = PREC_NAMES.get(prec, prec)
+    on, _, xcd, ll = dwf_tune_get(ctx, P, Ls, kernel_id=BATCH_INTERLEAVED)
+    if on > 0 and Ls in (8, 16, 32):
+        return {"mode": "interleaved", "spb": 1, "xcd": xcd, "ll": ll}
+    spb, _, xcd, ll = dwf_tune_get(ctx, P, Ls, kernel_id=BATCH_SEPARATE)
+    return {"mode": "separate", "spb": spb, "xcd": xcd, "ll": ll}

@@ -382,6 +382,156 @@ int launch_accumulate(Half<P64> hi, Half<Px> lo, long n5, int Ls, hipStream_t st
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// ------------------------------------------------------------- interleaved right-hand sides
+// Fields holding nrhs right-hand sides interleaved along s: slice s of right-hand side r is slice
+// r * RS + s of a field of extent LT = nrhs * RS (one thread per 5D site of the whole field).
+
+// p_out = r + beta_k p_in with beta_k = coef[k] of the slice's right-hand side k (0: p_in unread);
+// the first threads also record |r_k|^2 = coef[K + k] at scalars[k S_COUNT + S_RR]
+template <typename P>
+__global__ void __launch_bounds__(256) ilv_pupdate_kernel(CHalf<P> r, CHalf<P> pin, Half<P> pout, const double* coef,
+                                                           double* scalars, long n5, int LT, int RS) {
+  using R = typename P::R;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int K = LT / RS;
+  if (i < K) scalars[i * S_COUNT + S_RR] = coef[K + i];
+  if (i >= n5) return;
+  const double* betas = coef;
+  const long xs = i / LT;
+  const int s = int(i - xs * LT);
+  const double beta = betas[s / RS];
+  cx<R> rv[12], pv[12];
+  load_spinor<P>(r, xs, s, LT, rv);
+  if (beta != 0.0) {
+    load_spinor<P>(pin, xs, s, LT, pv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      pv[k].re = R(double(rv[k].re) + beta * double(pv[k].re));
+      pv[k].im = R(double(rv[k].im) + beta * double(pv[k].im));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pv[k] = rv[k];
+  }
+  store_spinor<P>(pout, xs, s, LT, pv);
+}
+
+template <typename P>
+int launch_ilv_pupdate(CHalf<P> r, CHalf<P> pin, Half<P> pout, const double* coef, double* scalars, long nsites, int LT,
+                       int RS, hipStream_t st) {
+  if (RS < 1 || LT % RS != 0 || pin.data == pout.data) return -1;
+  const long n5 = nsites * LT;
+  if (n5 <= 0) return 0;
+  hipLaunchKernelGGL((ilv_pupdate_kernel<P>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, r, pin, pout, coef,
+                     scalars, n5, LT, RS);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// x += sum_j alpha_{k,j} p_j, alpha_{k,j} = scalars[k S_COUNT + S_AHIST + slot_j] of the slice's
+// right-hand side k (the sum in FP64)
+template <typename P, typename Px>
+__global__ void __launch_bounds__(256) ilv_xflush_kernel(Half<Px> x, XFlush<P> f, const double* scalars, long n5,
+                                                          int LT, int RS) {
+  using RX = typename Px::R;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n5) return;
+  const long xs = i / LT;
+  const int s = int(i - xs * LT);
+  const double* sc = scalars + size_t(s / RS) * S_COUNT;
+  double sr[12], si[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) sr[k] = si[k] = 0.0;
+  for (int j = 0; j < f.n; ++j) {
+    const double a = sc[S_AHIST + f.slot[j]];
+    cx<typename P::R> pv[12];
+    load_spinor<P>(f.p[j], xs, s, LT, pv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      sr[k] += a * double(pv[k].re);
+      si[k] += a * double(pv[k].im);
+    }
+  }
+  cx<RX> xv[12];
+  load_spinor<Px>(CHalf<Px>{x.data, x.norm}, xs, s, LT, xv);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) xv[k] = {RX(double(xv[k].re) + sr[k]), RX(double(xv[k].im) + si[k])};
+  store_spinor<Px>(x, xs, s, LT, xv);
+}
+
+template <typename P, typename Px>
+int launch_ilv_xflush(Half<Px> x, const XFlush<P>& f, const double* scalars, long nsites, int LT, int RS,
+                      hipStream_t st) {
+  if (f.n < 0 || f.n > XFLUSH_MAX || RS < 1 || LT % RS != 0) return -1;
+  for (int j = 0; j < f.n; ++j)
+    if (f.slot[j] < 0 || f.slot[j] >= XFLUSH_MAX || !f.p[j].data) return -1;
+  const long n5 = nsites * LT;
+  if (n5 <= 0 || f.n == 0) return 0;
+  hipLaunchKernelGGL((ilv_xflush_kernel<P, Px>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, x, f, scalars,
+                     n5, LT, RS);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// segment r_out of out (extent LT_out) = segment r_in of in (extent LT_in), each of RS slices, with
+// conversion between storage precisions (a separate field is a single segment: r = 0, LT = RS)
+template <typename Pi, typename Po>
+__global__ void __launch_bounds__(256) ilv_move_kernel(CHalf<Pi> in, int LT_in, int r_in, Half<Po> out, int LT_out,
+                                                        int r_out, long n5, int RS) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n5) return;
+  const long xs = i / RS;
+  const int s = int(i - xs * RS);
+  cx<typename Pi::R> u[12];
+  cx<typename Po::R> v[12];
+  load_spinor<Pi>(in, xs, r_in * RS + s, LT_in, u);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = {typename Po::R(u[k].re), typename Po::R(u[k].im)};
+  store_spinor<Po>(out, xs, r_out * RS + s, LT_out, v);
+}
+
+template <typename Pi, typename Po>
+int launch_ilv_move(CHalf<Pi> in, int LT_in, int r_in, Half<Po> out, int LT_out, int r_out, long nsites, int RS,
+                    hipStream_t st) {
+  if (RS < 1 || r_in < 0 || r_out < 0 || (r_in + 1) * RS > LT_in || (r_out + 1) * RS > LT_out) return -1;
+  if (static_cast<const void*>(in.data) == static_cast<const void*>(out.data)) return -1;
+  const long n5 = nsites * RS;
+  if (n5 <= 0) return 0;
+  hipLaunchKernelGGL((ilv_move_kernel<Pi, Po>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, in, LT_in, r_in,
+                     out, LT_out, r_out, n5, RS);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// hi (a separate FP64 field of extent RS) += segment r of lo (extent LT); that segment = 0
+template <typename Px>
+__global__ void __launch_bounds__(256) ilv_accumulate_kernel(Half<P64> hi, Half<Px> lo, int LT, int r, long n5,
+                                                              int RS) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n5) return;
+  const long xs = i / RS;
+  const int s = int(i - xs * RS);
+  cx<double> h[12];
+  cx<typename Px::R> l[12];
+  load_spinor<P64>(CHalf<P64>{hi.data, nullptr}, xs, s, RS, h);
+  load_spinor<Px>(CHalf<Px>{lo.data, lo.norm}, xs, r * RS + s, LT, l);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    h[k].re += double(l[k].re);
+    h[k].im += double(l[k].im);
+    l[k] = {typename Px::R(0), typename Px::R(0)};
+  }
+  store_spinor<P64>(hi, xs, s, RS, h);
+  store_spinor<Px>(lo, xs, r * RS + s, LT, l);
+}
+
+template <typename Px>
+int launch_ilv_accumulate(Half<P64> hi, Half<Px> lo, int LT, int r, long nsites, int RS, hipStream_t st) {
+  if (RS < 1 || r < 0 || (r + 1) * RS > LT) return -1;
+  const long n5 = nsites * RS;
+  if (n5 <= 0) return 0;
+  hipLaunchKernelGGL((ilv_accumulate_kernel<Px>), dim3((unsigned)((n5 + 255) / 256)), dim3(256), 0, st, hi, lo, LT, r,
+                     n5, RS);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // zero fill with a kernel (also safe inside captured graphs)
 __global__ void __launch_bounds__(256) zero_kernel(uint32_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
@@ -526,5 +676,20 @@ template int launch_xflush<PB16, P32>(Half<P32>, const XFlush<PB16>&, const doub
 template int launch_accumulate<P32>(Half<P64>, Half<P32>, long, int, hipStream_t);
 template int launch_accumulate<P16>(Half<P64>, Half<P16>, long, int, hipStream_t);
 template int launch_accumulate<P64>(Half<P64>, Half<P64>, long, int, hipStream_t);
+
+#define DWF_INST_ILV(P, PX)                                                                                      \
+  template int launch_ilv_pupdate<P>(CHalf<P>, CHalf<P>, Half<P>, const double*, double*, long, int, int,       \
+                                     hipStream_t);                                                               \
+  template int launch_ilv_xflush<P, PX>(Half<PX>, const XFlush<P>&, const double*, long, int, int, hipStream_t); \
+  template int launch_ilv_move<P, P>(CHalf<P>, int, int, Half<P>, int, int, long, int, hipStream_t);
+DWF_INST_ILV(P64, P64)
+DWF_INST_ILV(P32, P32)
+DWF_INST_ILV(P16, P32)
+DWF_INST_ILV(PB16, P32)
+template int launch_ilv_move<P64, P32>(CHalf<P64>, int, int, Half<P32>, int, int, long, int, hipStream_t);
+template int launch_ilv_move<P64, P16>(CHalf<P64>, int, int, Half<P16>, int, int, long, int, hipStream_t);
+template int launch_ilv_move<P64, PB16>(CHalf<P64>, int, int, Half<PB16>, int, int, long, int, hipStream_t);
+template int launch_ilv_accumulate<P64>(Half<P64>, Half<P64>, int, int, long, int, hipStream_t);
+template int launch_ilv_accumulate<P32>(Half<P64>, Half<P32>, int, int, long, int, hipStream_t);
 
 }  // namespace dwf

@@ -446,13 +446,31 @@ int quotient_force(dwf_ctx* ctx, const dwf_params* p, int nq, const double* mass
 
 int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns, int xcd, int ll) {
   if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
-  if (kernel_id != 0 || prec < 0 || prec > 3 || Ls < 2 || Ls > 128) return fail(DWF_ERR_ARG, "bad tune key");
-  const long long key = (long long)prec * 100000 + Ls;
+  if (kernel_id < 0 || kernel_id > 2 || prec < 0 || prec > 3 || Ls < 2 || Ls > 128)
+    return fail(DWF_ERR_ARG, "bad tune key");
+  const long long key = tune_key(kernel_id, prec, Ls);
   if (spb == 0 && ns == 0) {
     ctx->tune.erase(key);
     return DWF_OK;
   }
+  if (kernel_id == 2) {
+    // the interleaved batched hop: spb 1 = on (workgroup shape fixed by the number of
+    // right-hand sides), -1 = off
+    if ((spb != 1 && spb != -1) || ns != 1 || (ll != 0 && ll != 1))
+      return fail(DWF_ERR_ARG, "interleaved hop: sites_per_block 1 (on) or -1 (off), s_per_thread 1, link_lds 0 or 1");
+    LaunchCfg c;
+    c.spb = 1;
+    c.ns = 1;
+    c.xcd = xcd ? 1 : 0;
+    c.ll = ll;
+    c.stage = 0;
+    c.off = spb < 0 ? 1 : 0;
+    ctx->tune[key] = c;
+    return DWF_OK;
+  }
   if (ns != 1 && ns != 2 && ns != 4) return fail(DWF_ERR_ARG, "s_per_thread must be 1, 2 or 4");
+  if (kernel_id == 1 && (ns != 1 || ll == 2))
+    return fail(DWF_ERR_ARG, "the batched hop runs one slice per thread without staged neighbours");
   if (Ls % ns != 0) return fail(DWF_ERR_ARG, "Ls must be divisible by s_per_thread");
   if (spb < 1 || spb * (Ls / ns) > 256) return fail(DWF_ERR_ARG, "sites_per_block * Ls / s_per_thread must be <= 256");
   const size_t elem = prec == DWF_FP64 ? 16 : 8;
@@ -475,8 +493,16 @@ int dwf_tune_set(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int spb, int ns,
 
 int dwf_tune_get(dwf_ctx* ctx, int kernel_id, int prec, int Ls, int* spb, int* ns, int* xcd, int* ll) {
   if (!ctx || !spb || !ns || !xcd || !ll) return fail(DWF_ERR_ARG, "NULL pointer");
-  if (kernel_id != 0 || prec < 0 || prec > 3 || Ls < 2) return fail(DWF_ERR_ARG, "bad tune key");
-  LaunchCfg c = hop_config(ctx, prec, Ls);
+  if (kernel_id < 0 || kernel_id > 2 || prec < 0 || prec > 3 || Ls < 2) return fail(DWF_ERR_ARG, "bad tune key");
+  if (kernel_id == 2) {
+    const LaunchCfg c = ilv_config(ctx, prec, Ls);
+    *spb = c.off ? -1 : 1;
+    *ns = 1;
+    *xcd = c.xcd;
+    *ll = c.ll;
+    return DWF_OK;
+  }
+  LaunchCfg c = kernel_id == 1 ? batch_config(ctx, prec, Ls) : hop_config(ctx, prec, Ls);
   *spb = c.spb;
   *ns = c.ns;
   *xcd = c.xcd;

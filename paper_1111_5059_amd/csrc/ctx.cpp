@@ -226,9 +226,32 @@ const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc) {
   return ctx->geoms.back().get();
 }
 
+static LaunchCfg default_config(int prec, int Ls);
+
 LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls) {
-  auto it = ctx->tune.find((long long)prec * 100000 + Ls);
+  auto it = ctx->tune.find(tune_key(0, prec, Ls));
   if (it != ctx->tune.end()) return it->second;
+  return default_config(prec, Ls);
+}
+
+// the batched hop (one launch over several fields): its own tuning entry, else the default shape
+LaunchCfg batch_config(dwf_ctx* ctx, int prec, int Ls) {
+  auto it = ctx->tune.find(tune_key(1, prec, Ls));
+  if (it != ctx->tune.end()) return it->second;
+  return default_config(prec, Ls);
+}
+
+LaunchCfg ilv_config(dwf_ctx* ctx, int prec, int Ls) {
+  auto it = ctx->tune.find(tune_key(2, prec, Ls));
+  if (it != ctx->tune.end()) return it->second;
+  LaunchCfg c = default_config(prec, Ls);
+  c.ns = 1;
+  c.stage = 0;
+  c.off = 0;
+  return c;
+}
+
+static LaunchCfg default_config(int prec, int Ls) {
   LaunchCfg c;
   c.ns = 1;
   c.xcd = 1;

@@ -400,8 +400,12 @@ constexpr int hop_min_waves() { return std::is_same<P, P16>::value && NS == 1 ? 
 // ST: neighbour spinors staged through LDS (FP16, compile-time Ls, one slice per lane, no
 // prologue, spb = 256 / Ls); its links are staged too (LL), so that the direction loop issues
 // no other vector-memory loads than the copies
-template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST>
-__global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
+// The body of the hop on workgroup bid of the field a (pidx: the slot of its norm partial).
+// RS > 0: the field holds Ls / RS right-hand sides of fifth-dimension extent RS interleaved along
+// s (slice s of right-hand side r is slice r RS + s), each with its own epilogue coefficients,
+// CG scalars and norm partials (see HopArgs).
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST, int RS = 0>
+__device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pidx, int spb) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
@@ -409,7 +413,18 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_ke
   const int Ls = LS > 0 ? LS : a.Ls, tps = Ls / NS;
   HopArgs<P> ak = a;
   ak.Ls = Ls;
-  const long bid = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+  // interleaved right-hand sides: their epilogue coefficients staged in LDS (read per lane there,
+  // instead of per-lane vector loads beside the gathers)
+  constexpr int NSEG = RS > 0 ? 256 / RS : 1;
+  __shared__ FifthScan<R> es_lds[(RS > 0 && EPI >= 2) ? (EPI == 3 ? 2 : 1) : 1][NSEG];
+  if constexpr (RS > 0 && EPI >= 2) {
+    const int K = Ls / RS;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+      es_lds[0][i] = a.es_tab[i];
+      if constexpr (EPI == 3) es_lds[1][i] = a.es2_tab[i];
+    }
+    __syncthreads();
+  }
   const int lsite = threadIdx.x / tps;
   const int s0 = threadIdx.x - lsite * tps;
   const long slot = bid * spb + lsite;
@@ -502,10 +517,16 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_ke
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
   }
+  // the lane's right-hand side and slice within it (interleaved fields)
+  const int rhs = RS > 0 ? s0 / (RS > 0 ? RS : 1) : 0;
+  const int sr = RS > 0 ? s0 - rhs * RS : s0;
   if constexpr (EPI >= 2) {
-    // recurrence form along s: the site's Ls lanes are one segment of the wave
-    static_assert(NS == 1 && LS > 0 && (64 % LS) == 0, "scan epilogue needs one slice per lane");
-    fifth_scan_apply<LS>(acc[0], s0, a.es);
+    // recurrence form along s: the site's Ls lanes (a right-hand side's RS lanes) are one
+    // segment of the wave
+    constexpr int SEG = RS > 0 ? RS : LS;
+    static_assert(NS == 1 && SEG > 0 && (64 % SEG) == 0, "scan epilogue needs one slice per lane");
+    if constexpr (RS > 0) fifth_scan_apply<SEG>(acc[0], sr, es_lds[0][rhs]);
+    else fifth_scan_apply<SEG>(acc[0], s0, a.es);
   }
   if constexpr (EPI == 1) {
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
@@ -548,7 +569,7 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_ke
   }
   double nrm = 0.0;
   if (active) {
-    const R alpha = CG ? R(a.cg_scalars[S_ALPHA]) : R(0);
+    const R alpha = CG ? R(a.cg_scalars[rhs * S_COUNT + S_ALPHA]) : R(0);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const int s = s0 + j * tps;
@@ -583,12 +604,106 @@ __global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_ke
   if constexpr (EPI == 3 && !CG) {
     // second output: the site-local operator es2 on the final result (all lanes of a site
     // are active or inactive together, so the segment shuffles stay within active lanes)
-    fifth_scan_apply<LS>(acc[0], s0, a.es2);
+    constexpr int SEG = RS > 0 ? RS : LS;
+    if constexpr (RS > 0) fifth_scan_apply<SEG>(acc[0], sr, es_lds[EPI == 3 ? 1 : 0][rhs]);
+    else fifth_scan_apply<SEG>(acc[0], s0, a.es2);
     if (active) store_spinor<P>(a.out2, x, s0, Ls, acc[0]);
   }
   if (a.norm_partials) {
-    const double t = block_sum(nrm, red);
-    if (threadIdx.x == 0) a.norm_partials[blockIdx.x] = t;
+    if constexpr (RS > 0) {
+      // per right-hand side: the sum over its segment (butterfly within the RS lanes), then over
+      // the workgroup's sites; partial of right-hand side r at norm_partials[r part_stride + pidx]
+      static_assert(NS == 1 && (64 % (RS > 0 ? RS : 1)) == 0, "interleaved right-hand sides: one slice per lane");
+      __shared__ double redr[256 / (RS > 0 ? RS : 1)];
+      double v = nrm;
+#pragma unroll
+      for (int off = 1; off < RS; off <<= 1) v += __shfl_xor(v, off, 64);
+      if (sr == 0) redr[threadIdx.x / RS] = v;
+      __syncthreads();
+      const int K = Ls / RS;
+      if (int(threadIdx.x) < K) {
+        double t = 0.0;
+        for (int j = 0; j < spb; ++j) t += redr[j * K + threadIdx.x];
+        a.norm_partials[threadIdx.x * a.part_stride + pidx] = t;
+      }
+    } else {
+      const double t = block_sum(nrm, red);
+      if (threadIdx.x == 0) a.norm_partials[pidx] = t;
+    }
+  }
+}
+
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST>
+__global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>())) hop_kernel(HopArgs<P> a, int spb, int xcd) {
+  const long bid = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+  hop_body<P, LS, NS, DAG, PRO, EPI, LL, CG, ST>(a, bid, blockIdx.x, spb);
+}
+
+// Several fields (right-hand sides) of one lattice in one launch: workgroup b takes field
+// b % nrhs and site block b / nrhs, so that the nrhs workgroups of one site block are dispatched
+// together (and, with the XCD-aware order, on one XCD): the links of those sites are read once
+// from memory and then hit in that XCD's L2 for the other fields.  args: device table of the
+// fields' arguments (the same kernel variant for all of them); each field's norm partials are
+// indexed by its site block.
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST>
+__global__ void __launch_bounds__(256, (hop_min_waves<P, NS, EPI, CG>()))
+    hop_batch_kernel(const HopArgs<P>* __restrict__ args, int nrhs, int spb, int xcd) {
+  const long b = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+  const long bid = b / nrhs;
+  hop_body<P, LS, NS, DAG, PRO, EPI, LL, CG, ST>(args[b - bid * nrhs], bid, bid, spb);
+}
+
+// Right-hand sides interleaved along the fifth dimension (segments of RS slices, a.Ls = their
+// number times RS; no Moebius prologue): one slice per lane, the site's a.Ls lanes contiguous.
+template <typename P, bool DAG, int EPI, bool LL, bool CG, int RS>
+__global__ void __launch_bounds__(256, (hop_min_waves<P, 1, EPI, CG>())) hop_ilv_kernel(HopArgs<P> a, int spb, int xcd) {
+  const long bid = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+  hop_body<P, 0, 1, DAG, false, EPI, LL, CG, false, RS>(a, bid, blockIdx.x, spb);
+}
+
+template <typename P, bool DAG, int EPI, bool CG, int RS>
+static int launch_ilv_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
+  const int threads = cfg.spb * a.Ls;
+  const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
+  const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, false);
+  if (cfg.ll)
+    hipLaunchKernelGGL((hop_ilv_kernel<P, DAG, EPI, true, CG, RS>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
+                       cfg.spb, cfg.xcd);
+  else
+    hipLaunchKernelGGL((hop_ilv_kernel<P, DAG, EPI, false, CG, RS>), dim3((unsigned)blocks), dim3(threads), lds, st, a,
+                       cfg.spb, cfg.xcd);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename P, int RS>
+static int launch_ilv_rs(const HopArgs<P>& a, bool dag, const LaunchCfg& cfg, hipStream_t st) {
+  const bool epi = a.epi_scan != 0;
+  if (dag) {
+    if (a.cg_r.data) return epi ? -1 : launch_ilv_t<P, true, 0, true, RS>(a, cfg, st);
+    return epi ? launch_ilv_t<P, true, 2, false, RS>(a, cfg, st) : launch_ilv_t<P, true, 0, false, RS>(a, cfg, st);
+  }
+  if (!epi) return a.out2.data ? -1 : launch_ilv_t<P, false, 0, false, RS>(a, cfg, st);
+  return a.out2.data ? launch_ilv_t<P, false, 3, false, RS>(a, cfg, st) : launch_ilv_t<P, false, 2, false, RS>(a, cfg, st);
+}
+
+// The hop on a field of right-hand sides interleaved along s in segments of rs slices (8, 16
+// or 32): a.Ls = nrhs rs, the epilogue (a.epi_scan) from a.es_tab / a.es2_tab (one entry per
+// right-hand side), the fused CG step's alpha of right-hand side r at a.cg_scalars[r S_COUNT +
+// S_ALPHA], norm partials at a.norm_partials[r a.part_stride + block].  Validates the shape:
+// one slice per thread, a.Ls * sites per workgroup <= 256, no dense epilogue, no prologue.
+template <typename P>
+int launch_hop_ilv(const HopArgs<P>& a, bool dagger, int rs, const LaunchCfg& cfg, hipStream_t st) {
+  if (rs != 8 && rs != 16 && rs != 32) return -1;
+  if (a.Ls < rs || a.Ls % rs != 0 || cfg.ns != 1 || cfg.spb < 1 || cfg.spb * a.Ls > 256) return -1;
+  if (a.E || (a.epi_scan && !a.es_tab) || (a.out2.data && (!a.epi_scan || !a.es2_tab || dagger))) return -1;
+  if (a.cg_r.data && (!dagger || !a.cg_scalars)) return -1;
+  if (a.norm_partials && a.part_stride < (a.nsites + cfg.spb - 1) / cfg.spb) return -1;
+  if (hop_lds_bytes<P>(cfg, a.Ls, false) > 65536) return -1;
+  if (a.nsites <= 0) return 0;
+  switch (rs) {
+    case 8: return launch_ilv_rs<P, 8>(a, dagger, cfg, st);
+    case 16: return launch_ilv_rs<P, 16>(a, dagger, cfg, st);
+    default: return launch_ilv_rs<P, 32>(a, dagger, cfg, st);
   }
 }
 
@@ -598,11 +713,28 @@ constexpr bool stage_capable() {
   return std::is_same<P, P16>::value && NS == 1 && !PRO && EPI != 1 && (LS == 8 || LS == 16 || LS == 32);
 }
 
+// batch (device table of nrhs fields' arguments, a = the host copy of the first): one launch over
+// all of them (one slice per thread, no LDS-staged neighbours)
 template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool CG>
-static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
+static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st, const HopArgs<P>* batch,
+                        int nrhs) {
   const int tps = a.Ls / NS;
   const int threads = cfg.spb * tps;
   const long blocks = (a.nsites + cfg.spb - 1) / cfg.spb;
+  if (batch) {
+    if constexpr (NS == 1) {
+      const size_t lds = hop_lds_bytes<P>(cfg, a.Ls, EPI == 1);
+      if (cfg.ll)
+        hipLaunchKernelGGL((hop_batch_kernel<P, LS, NS, DAG, PRO, EPI, true, CG, false>),
+                           dim3((unsigned)(blocks * nrhs)), dim3(threads), lds, st, batch, nrhs, cfg.spb, cfg.xcd);
+      else
+        hipLaunchKernelGGL((hop_batch_kernel<P, LS, NS, DAG, PRO, EPI, false, CG, false>),
+                           dim3((unsigned)(blocks * nrhs)), dim3(threads), lds, st, batch, nrhs, cfg.spb, cfg.xcd);
+      return hipGetLastError() == hipSuccess ? 0 : -2;
+    } else {
+      return -1;
+    }
+  }
   if constexpr (stage_capable<P, LS, NS, PRO, EPI>()) {
     if (stage_shape(cfg, a.Ls)) {
       LaunchCfg c2 = cfg;
@@ -626,46 +758,53 @@ static int launch_hop_t(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t s
 // second, scanned output (only where the site's Ls slices form one wave segment).  An epilogue
 // is given by its matrices E, by its recurrence form (epi_scan) or both; the dense form needs E.
 template <typename P, int LS, int NS, bool DAG, bool PRO, bool CG>
-static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st) {
-  if (!a.E && !a.epi_scan) return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st);
+static int launch_hop_epi(const HopArgs<P>& a, const LaunchCfg& cfg, hipStream_t st, const HopArgs<P>* batch,
+                          int nrhs) {
+  if (!a.E && !a.epi_scan) return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 0, CG>(a, cfg, st, batch, nrhs);
   if constexpr (NS == 1 && (LS == 8 || LS == 16 || LS == 32)) {
     if (a.epi_scan) {
       if constexpr (!DAG && !CG) {
-        if (a.out2.data) return launch_hop_t<P, LS, NS, DAG, PRO, 3, CG>(a, cfg, st);
+        if (a.out2.data) return launch_hop_t<P, LS, NS, DAG, PRO, 3, CG>(a, cfg, st, batch, nrhs);
       }
-      return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 2, CG>(a, cfg, st);
+      return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 2, CG>(a, cfg, st, batch, nrhs);
     }
   }
   if (!a.E) return -1;  // the recurrence form does not apply to this launch shape
-  return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 1, CG>(a, cfg, st);
+  return a.out2.data ? -1 : launch_hop_t<P, LS, NS, DAG, PRO, 1, CG>(a, cfg, st, batch, nrhs);
 }
 
 // the fused CG step exists for the dagger hop only (the last hop of M^dag M)
 template <typename P, int LS, int NS>
-static int launch_hop_ns(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
+static int launch_hop_ns(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st,
+                         const HopArgs<P>* batch, int nrhs) {
   if (dag) {
-    if (a.cg_r.data) return launch_hop_epi<P, LS, NS, true, false, true>(a, cfg, st);
-    return launch_hop_epi<P, LS, NS, true, false, false>(a, cfg, st);
+    if (a.cg_r.data) return launch_hop_epi<P, LS, NS, true, false, true>(a, cfg, st, batch, nrhs);
+    return launch_hop_epi<P, LS, NS, true, false, false>(a, cfg, st, batch, nrhs);
   }
-  if (pro) return launch_hop_epi<P, LS, NS, false, true, false>(a, cfg, st);
-  return launch_hop_epi<P, LS, NS, false, false, false>(a, cfg, st);
+  if (pro) return launch_hop_epi<P, LS, NS, false, true, false>(a, cfg, st, batch, nrhs);
+  return launch_hop_epi<P, LS, NS, false, false, false>(a, cfg, st, batch, nrhs);
 }
 
 // One compile-time fifth-dimension extent (0: runtime extent).  Each (precision, LS)
 // pair is instantiated in its own translation unit (see the build script).
 template <typename P, int LS>
-int launch_hop_ls(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st) {
+int launch_hop_ls(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, hipStream_t st,
+                  const HopArgs<P>* batch, int nrhs) {
   switch (cfg.ns) {
-    case 1: return launch_hop_ns<P, LS, 1>(a, dag, pro, cfg, st);
-    case 2: return launch_hop_ns<P, LS, 2>(a, dag, pro, cfg, st);
-    default: return launch_hop_ns<P, LS, 4>(a, dag, pro, cfg, st);
+    case 1: return launch_hop_ns<P, LS, 1>(a, dag, pro, cfg, st, batch, nrhs);
+    case 2: return launch_hop_ns<P, LS, 2>(a, dag, pro, cfg, st, batch, nrhs);
+    default: return launch_hop_ns<P, LS, 4>(a, dag, pro, cfg, st, batch, nrhs);
   }
 }
 
 // Validates the launch shape against the kernel's assumptions before launching:
 // Ls divisible by NS, at most 256 threads per workgroup, LDS within 64 KiB.
+// batch != nullptr: one launch over nrhs fields (device table; a = the host copy of the first,
+// which fixes the kernel variant: every field must have the same Ls, nsites and optional stages);
+// one slice per thread only, no LDS-staged neighbours.
 template <typename P>
-int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st) {
+int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st,
+               const HopArgs<P>* batch, int nrhs) {
   using R = typename P::R;
   if (cfg.ns != 1 && cfg.ns != 2 && cfg.ns != 4) return -1;
   if (a.Ls % cfg.ns != 0 || cfg.spb < 1) return -1;
@@ -675,14 +814,15 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
   if (threads > 256) return -1;
   if (hop_lds_bytes<P>(cfg, a.Ls, a.E != nullptr) > 65536) return -1;
   if (a.epi_scan && !a.E && !(cfg.ns == 1 && (a.Ls == 8 || a.Ls == 16 || a.Ls == 32))) return -1;
+  if (batch && (nrhs < 1 || cfg.ns != 1 || stage_shape(cfg, a.Ls))) return -1;
   if (a.nsites <= 0) return 0;
   // common extents get a compile-time Ls; the others run the generic kernel
   switch (a.Ls) {
-    case 8: return launch_hop_ls<P, 8>(a, dagger, prologue, cfg, st);
-    case 12: return launch_hop_ls<P, 12>(a, dagger, prologue, cfg, st);
-    case 16: return launch_hop_ls<P, 16>(a, dagger, prologue, cfg, st);
-    case 32: return launch_hop_ls<P, 32>(a, dagger, prologue, cfg, st);
-    default: return launch_hop_ls<P, 0>(a, dagger, prologue, cfg, st);
+    case 8: return launch_hop_ls<P, 8>(a, dagger, prologue, cfg, st, batch, nrhs);
+    case 12: return launch_hop_ls<P, 12>(a, dagger, prologue, cfg, st, batch, nrhs);
+    case 16: return launch_hop_ls<P, 16>(a, dagger, prologue, cfg, st, batch, nrhs);
+    case 32: return launch_hop_ls<P, 32>(a, dagger, prologue, cfg, st, batch, nrhs);
+    default: return launch_hop_ls<P, 0>(a, dagger, prologue, cfg, st, batch, nrhs);
   }
 }
 
@@ -817,13 +957,17 @@ inline long fifth_blocks(long nsites, int Ls, size_t elem) {
 
 }  // namespace dwf
 
-#define DWF_HOP_LS_ONE(P, L) \
-  template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);
-#define DWF_HOP_LS_EXTERN(P, L) \
-  extern template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);
+#define DWF_HOP_LS_ONE(P, L)                                                                           \
+  template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t, \
+                                        const HopArgs<P>*, int);
+#define DWF_HOP_LS_EXTERN(P, L)                                                                               \
+  extern template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t, \
+                                               const HopArgs<P>*, int);
 #define DWF_INSTANTIATE_HOP(P)                                                                                   \
   DWF_HOP_LS_EXTERN(P, 0) DWF_HOP_LS_EXTERN(P, 8) DWF_HOP_LS_EXTERN(P, 12) DWF_HOP_LS_EXTERN(P, 16)               \
   DWF_HOP_LS_EXTERN(P, 32)                                                                                      \
-  template int dwf::launch_hop<P>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t);                \
+  template int dwf::launch_hop<P>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t,                \
+                                  const HopArgs<P>*, int);                                                      \
+  template int dwf::launch_hop_ilv<P>(const HopArgs<P>&, bool, int, const LaunchCfg&, hipStream_t);             \
   template int dwf::launch_fifth<P>(CHalf<P>, Half<P>, const P::R*, const FifthScan<P::R>*, CHalf<P>, P::R,   \
                                     long, int, double*, hipStream_t);

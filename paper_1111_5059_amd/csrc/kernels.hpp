@@ -54,6 +54,11 @@ struct HopArgs {
   // iterations at a time).
   Half<P> cg_r = {nullptr, nullptr};
   const double* cg_scalars = nullptr;
+  // right-hand sides interleaved along s (launch_hop_ilv): per right-hand side epilogue
+  // coefficients (device tables) and the stride of the norm partials between right-hand sides
+  const FifthScan<typename P::R>* es_tab = nullptr;
+  const FifthScan<typename P::R>* es2_tab = nullptr;
+  long part_stride = 0;
 };
 
 struct LaunchCfg {
@@ -62,14 +67,22 @@ struct LaunchCfg {
   int xcd;        // XCD-aware block order
   int ll;         // links staged in LDS
   int stage = 0;  // neighbour spinors (and links) staged through LDS (FP16, Ls 8/16/32, spb = 256/Ls, ns 1)
+  int off = 0;    // (the interleaved batched hop's entry) interleaving switched off
 };
 // the launch shape the LDS-staged hop runs with
 inline bool stage_shape(const LaunchCfg& cfg, int Ls) {
   return cfg.stage && cfg.ns == 1 && cfg.spb * Ls == 256 && (Ls == 8 || Ls == 16 || Ls == 32);
 }
 
+// batch: optional device table of nrhs fields' arguments for one launch over all of them (a is
+// then the host copy of the first)
 template <typename P>
-int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st);
+int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg& cfg, hipStream_t st,
+               const HopArgs<P>* batch = nullptr, int nrhs = 1);
+
+// the hop on right-hand sides interleaved along s in segments of rs slices (see hop_impl.hpp)
+template <typename P>
+int launch_hop_ilv(const HopArgs<P>& a, bool dagger, int rs, const LaunchCfg& cfg, hipStream_t st);
 
 // out = ax * x + E . in  (site-local fifth-dimension matrices), optional |out|^2 partials
 template <typename P>
@@ -126,6 +139,24 @@ int launch_slice_copy(CHalf<P64> in, int Ls_in, int s_in, Half<P64> out, int Ls_
 template <typename Px>
 int launch_accumulate(Half<P64> hi, Half<Px> lo, long n5, int Ls, hipStream_t st);
 int launch_zero(void* p, size_t bytes, hipStream_t st);
+// Fields of several right-hand sides interleaved along s: slice s of right-hand side r is slice
+// r RS + s of a field of extent LT (a separate field: r = 0, LT = RS).
+// p_out = r + coef[k] p_in per right-hand side k (device table; 0: p_in unread), and
+// scalars[k S_COUNT + S_RR] = coef[K + k] (K = LT / RS)
+template <typename P>
+int launch_ilv_pupdate(CHalf<P> r, CHalf<P> pin, Half<P> pout, const double* coef, double* scalars, long nsites, int LT,
+                       int RS, hipStream_t st);
+// x += sum_j alpha_{k,j} p_j with alpha_{k,j} = scalars[k S_COUNT + S_AHIST + slot_j]
+template <typename P, typename Px>
+int launch_ilv_xflush(Half<Px> x, const XFlush<P>& f, const double* scalars, long nsites, int LT, int RS,
+                      hipStream_t st);
+// segment r_out of out = segment r_in of in (precision conversion), out-of-place
+template <typename Pi, typename Po>
+int launch_ilv_move(CHalf<Pi> in, int LT_in, int r_in, Half<Po> out, int LT_out, int r_out, long nsites, int RS,
+                    hipStream_t st);
+// hi (separate FP64 field, extent RS) += segment r of lo (extent LT); the segment is zeroed
+template <typename Px>
+int launch_ilv_accumulate(Half<P64> hi, Half<Px> lo, int LT, int r, long nsites, int RS, hipStream_t st);
 int launch_set_scalar(double* scalars, int slot, double v, hipStream_t st);
 
 // ---------------------------------------------------------------- packing

@@ -109,7 +109,13 @@ int dslash_noalloc(dwf_ctx* ctx, const dwf_params& p, const void* U, const void*
 const Geometry* geometry(dwf_ctx* ctx, const int dims[4], int tbc);
 // traversal tile of the hop kernels on one lattice (0, 0, 0: the default)
 void set_tile(dwf_ctx* ctx, const int dims[4], int tbc, const int tile[3]);
+// launch configuration of the hop (kernel 0) and of the batched hop (kernel 1) for (prec, Ls):
+// the tuned entry, else the default shape (one slice per thread)
+inline long long tune_key(int kernel, int prec, int Ls) { return (long long)kernel * 1000000 + prec * 100000 + Ls; }
 LaunchCfg hop_config(dwf_ctx* ctx, int prec, int Ls);
+LaunchCfg batch_config(dwf_ctx* ctx, int prec, int Ls);
+// the interleaved batched hop (kernel 2): XCD order, link staging, or off (separate fields)
+LaunchCfg ilv_config(dwf_ctx* ctx, int prec, int Ls);
 // device buffer of the fifth-dimension matrices for one parameter set
 // (bs, cs: optional s-dependent Moebius coefficients, Ls entries each)
 const void* fifth_matrices(dwf_ctx* ctx, int Ls, double M5, double m, double b, double c, int prec,
@@ -202,10 +208,10 @@ struct Op {
     const double* scalars = nullptr;
   };
 
-  // out2 (optional): slot2 applied to the final result, a second output of the same launch
-  void hop(int out_par, CHalf<P> in, Half<P> out, bool dag, bool pro, double scale, const R* epi,
-           CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr,
-           const CgStep& cg = CgStep(), Half<P> out2 = {nullptr, nullptr}, int slot2 = 0) const {
+  // the launch arguments of one hop (see hop)
+  HopArgs<P> hop_args(int out_par, CHalf<P> in, Half<P> out, const R* epi, double scale,
+                      CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr,
+                      const CgStep& cg = CgStep(), Half<P> out2 = {nullptr, nullptr}, int slot2 = 0) const {
     HopArgs<P> a;
     a.out2 = out2;
     if (out2.data) a.es2 = es[slot2];
@@ -235,24 +241,36 @@ struct Op {
     a.x = x;
     a.ax = R(ax);
     a.norm_partials = partials;
-    long mark = -1;
-    if (ctx->timer.on) mark = timer_begin(ctx, hop_name(a, dag, pro && moebius));
-    DWF_CHECK_LAUNCH(launch_hop<P>(a, dag, pro && moebius, cfg, ctx->stream));
-    if (mark >= 0) {
-      // fields read and written once: in, out (or with the CG step: r read and written), x
-      const double fb = spinor_site_bytes<P>();
-      const double bytes = cg.r.data ? fb * (3 + (x.data ? 1 : 0)) : fb * (2 + (x.data ? 1 : 0) + (out2.data ? 1 : 0));
-      timer_end(ctx, mark, double(n5()) * bytes + double(g->nsites) * 72 * sizeof(S));
-    }
+    return a;
   }
-  // the template instance launch_hop selects for these arguments (kernel name as demangled)
-  std::string hop_name(const HopArgs<P>& a, bool dag, bool pro) const {
+  // algorithmic bytes of one hop launch: fields read and written once (in, out -- or with the CG
+  // step r read and written --, the axpy operand, the second output) and the links once
+  double hop_bytes(const HopArgs<P>& a) const {
+    const double fb = spinor_site_bytes<P>();
+    const bool xin = a.x.data != nullptr;
+    const double bytes = a.cg_r.data ? fb * (3 + (xin ? 1 : 0)) : fb * (2 + (xin ? 1 : 0) + (a.out2.data ? 1 : 0));
+    return double(n5()) * bytes + double(g->nsites) * 72 * sizeof(S);
+  }
+  // out2 (optional): slot2 applied to the final result, a second output of the same launch
+  void hop(int out_par, CHalf<P> in, Half<P> out, bool dag, bool pro, double scale, const R* epi,
+           CHalf<P> x = {nullptr, nullptr}, double ax = 0.0, double* partials = nullptr,
+           const CgStep& cg = CgStep(), Half<P> out2 = {nullptr, nullptr}, int slot2 = 0) const {
+    const HopArgs<P> a = hop_args(out_par, in, out, epi, scale, x, ax, partials, cg, out2, slot2);
+    long mark = -1;
+    if (ctx->timer.on) mark = timer_begin(ctx, hop_name(a, dag, pro && moebius, cfg));
+    DWF_CHECK_LAUNCH(launch_hop<P>(a, dag, pro && moebius, cfg, ctx->stream));
+    if (mark >= 0) timer_end(ctx, mark, hop_bytes(a));
+  }
+  // the template instance launch_hop selects for these arguments and launch shape (kernel name as
+  // demangled; batch: the batched kernel)
+  std::string hop_name(const HopArgs<P>& a, bool dag, bool pro, const LaunchCfg& cfg, bool batch = false) const {
     const int ls = (Ls == 8 || Ls == 12 || Ls == 16 || Ls == 32) ? Ls : 0;
     int epi = 0;
     if (a.E) epi = (a.epi_scan && cfg.ns == 1 && (ls == 8 || ls == 16 || ls == 32)) ? (a.out2.data ? 3 : 2) : 1;
-    const bool st = P::ID == DWF_FP16 && cfg.ns == 1 && !pro && epi != 1 && (ls == 8 || ls == 16 || ls == 32) &&
-                    stage_shape(cfg, Ls);
-    return std::string("hop_kernel<") + prec_tag(P::ID) + ", " + std::to_string(ls) + ", " + std::to_string(cfg.ns) +
+    const bool st = !batch && P::ID == DWF_FP16 && cfg.ns == 1 && !pro && epi != 1 &&
+                    (ls == 8 || ls == 16 || ls == 32) && stage_shape(cfg, Ls);
+    return std::string(batch ? "hop_batch_kernel<" : "hop_kernel<") + prec_tag(P::ID) + ", " + std::to_string(ls) +
+           ", " + std::to_string(cfg.ns) +
            ", " + (dag ? "true" : "false") + ", " + (pro ? "true" : "false") + ", " + std::to_string(epi) + ", " +
            (cfg.ll || st ? "true" : "false") + ", " + (a.cg_r.data ? "true" : "false") + ", " +
            (st ? "true" : "false") + ">";

@@ -9,7 +9,6 @@
 #include <chrono>
 #include "runtime.hpp"
 #include "solver.hpp"
-#include "batch.hpp"
 
 namespace dwf {
 
@@ -299,10 +298,12 @@ int solve_full(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b
 
 // ------------------------------------------------------------------ batched CG
 // Several right-hand sides (the Hasenbusch mass ladder of Sec. 3; possibly on different
-// lattices) iterate together: every hop stage of M_prec and M_prec^dag is one launch over all
-// unconverged right-hand sides (links staged once per workgroup for all right-hand sides of a
-// lattice), and one device-to-host copy per iteration returns every residual norm.  The
-// per-RHS logic (FP64 scalars, reliable updates, convergence) is that of cg_normal.
+// lattices) iterate in lock step, each with the iteration of cg_normal (the same fused hops,
+// direction ring and deferred increment, FP64 scalars and reliable updates).  Each of the four
+// hop stages of an iteration is one launch over the unconverged right-hand sides of a lattice
+// (hop_batch_kernel: the right-hand sides of one site block run together, so its links are
+// read from memory once and then hit in L2); one device-to-host copy per iteration returns
+// every residual.
 struct BatchSys {
   dwf_params p;
   const Geometry* g;
@@ -315,29 +316,383 @@ struct BatchSys {
   int cap = 0;  // iterations this system may still run
   bool active = false;
   SolveStats st;
-  // inner vectors (storage precision of the solve)
-  void *r = nullptr, *pv = nullptr, *q = nullptr, *Ap = nullptr, *te = nullptr, *xl = nullptr;
-  const void* E = nullptr;  // fifth-dimension matrices of this mass
-  int group = -1;
 };
 
+// The right-hand sides of one lattice with Ls = RS in {8, 16, 32}, Shamir operator, interleaved
+// along the fifth dimension: every vector of the iteration is one field of extent K RS (slice s of
+// right-hand side r at r RS + s), so that each hop stage is one launch whose workgroups take all K
+// right-hand sides of a site (the site's neighbour indices and links serve K RS lanes, each
+// neighbour's K RS slices are one contiguous gather).  The fifth-dimension blocks, CG scalars and
+// norm partials are per right-hand side.  When a right-hand side converges it leaves the field
+// (the others are moved together); the FP64 solutions, residuals and reliable updates stay
+// separate per right-hand side.
 template <typename Pi>
-static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double delta) {
+static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delta) {
   constexpr bool MIXED = !std::is_same<Pi, P64>::value;
-  using PX = typename std::conditional<MIXED, P32, P64>::type;
+  using PX = typename IncrementPrec<Pi>::type;
   using R = typename Pi::R;
+  using SS = typename Pi::S;
   constexpr bool RESTART = std::is_same<Pi, PB16>::value;
+  constexpr int KX = 8;
+  hipStream_t s = ctx->stream;
+  const int K0 = int(sys.size());
+  const Geometry* g = sys[0]->g;
+  const int RS = sys[0]->p.Ls;
+  const long ns = g->nsites;
+  const int LT0 = K0 * RS;
+  // launch shape: the whole site (LT lanes) in a workgroup; LDS link staging and XCD order from
+  // the interleaved hop's tuning entry
+  const LaunchCfg tuned = ilv_config(ctx, Pi::ID, RS);
+  auto cfg_for = [&](int LT) {
+    LaunchCfg c;
+    c.ns = 1;
+    c.spb = std::max(1, 256 / LT);
+    c.xcd = tuned.xcd;
+    c.ll = tuned.ll;
+    c.stage = 0;
+    return c;
+  };
+  const long pstride = (ns + cfg_for(LT0).spb - 1) / cfg_for(LT0).spb;
+  double* part = reinterpret_cast<double*>(ws_get(ctx, "ilv.partials", size_t(K0) * pstride * sizeof(double)));
+  double* sc = reinterpret_cast<double*>(ws_get(ctx, "ilv.scalars", size_t(K0) * S_COUNT * sizeof(double)));
+  double* dcoef = reinterpret_cast<double*>(ws_get(ctx, "ilv.coef", size_t(2) * K0 * sizeof(double)));
+  const size_t nscan = size_t(3) * K0;
+  FifthScan<R>* dscan = reinterpret_cast<FifthScan<R>*>(ws_get(ctx, "ilv.scan", nscan * sizeof(FifthScan<R>)));
+  // pinned host mirrors: scalars, p-update coefficients, fifth-dimension tables
+  double* hsc = nullptr;
+  double* hcoef = nullptr;
+  FifthScan<R>* hscan = nullptr;
+  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsc), size_t(K0) * S_COUNT * sizeof(double)));
+  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hcoef), size_t(2) * K0 * sizeof(double)));
+  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hscan), nscan * sizeof(FifthScan<R>)));
+  struct HostFree {
+    void* p[3];
+    ~HostFree() {
+      for (void* q : p)
+        if (q) (void)hipHostFree(q);
+    }
+  } host_free{{hsc, hcoef, hscan}};
+  // interleaved inner vectors (sized for all K0 right-hand sides)
+  const size_t hbi = half_bytes<Pi>(ns, LT0);
+  void* rb = ws_get(ctx, "ilv.r", hbi);
+  void* qb = ws_get(ctx, "ilv.q", hbi);
+  void* teb = ws_get(ctx, "ilv.te", hbi);
+  void* tob = ws_get(ctx, "ilv.to", hbi);
+  void* pb[KX];
+  for (int j = 0; j < KX; ++j) pb[j] = ws_get(ctx, "ilv.p" + std::to_string(j), hbi);
+  void* xlb = MIXED ? ws_get(ctx, "ilv.xlo", half_bytes<PX>(ns, LT0)) : nullptr;
+  // FP64 per-right-hand-side solution increment for FP64 iterations (PX = P64): kept interleaved too
+  if (!MIXED) xlb = ws_get(ctx, "ilv.x64", half_bytes<PX>(ns, LT0));
+  const size_t hb64 = half_size<P64>(g, RS);
+  void* rhi_raw = ws_get(ctx, "ilv.rhi", hb64);
+  void* t64a_raw = ws_get(ctx, "ilv.t64a", hb64);
+  void* t64b_raw = ws_get(ctx, "ilv.t64b", hb64);
+  void* t64c_raw = ws_get(ctx, "ilv.t64c", hb64);
+  auto true_residual = [&](BatchSys& b) -> double {
+    Half<P64> rhi = hview<P64>(rhi_raw, g, RS), ta = hview<P64>(t64a_raw, g, RS), tb = hview<P64>(t64b_raw, g, RS),
+              tc = hview<P64>(t64c_raw, g, RS);
+    b.op64->mprec(cv(b.x), ta, tb);
+    b.op64->mprec_dag(cv(ta), rhi, tb, tc);
+    DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, b.rhs, -1.0, rhi, ns * RS, RS, s));
+    return norm2_sync<P64>(ctx, cv(rhi), g, RS);
+  };
+  auto H = [&](void* base, int LT) { return half_view<Pi>(base, ns, LT); };
+  auto HX = [&](void* base, int LT) { return half_view<PX>(base, ns, LT); };
+  // the operators in the iteration precision (fifth-dimension coefficients per mass)
+  std::vector<std::unique_ptr<Op<Pi>>> ops(K0);
+  for (int k = 0; k < K0; ++k) ops[k] = std::make_unique<Op<Pi>>(ctx, g, sys[k]->p, sys[k]->Ui);
+  const SS* links = reinterpret_cast<const SS*>(sys[0]->Ui);
+  // start: the residual of every system into its segment
+  std::vector<int> seg;  // segment -> system
+  int LT = LT0;
+  DWF_CHECK_LAUNCH(launch_zero(xlb, half_bytes<PX>(ns, LT0), s));
+  for (int k = 0; k < K0; ++k) {
+    BatchSys& b = *sys[k];
+    b.rhs2 = norm2_sync<P64>(ctx, b.rhs, g, RS);
+    b.target = b.tol_n * b.tol_n * b.rhs2;
+    b.active = false;
+    if (b.rhs2 == 0.0) {
+      DWF_CHECK_LAUNCH(launch_zero(b.x.data, hb64, s));
+      continue;
+    }
+    CHalf<P64> r0 = b.rhs;
+    if (norm2_sync<P64>(ctx, cv(b.x), g, RS) == 0.0) {
+      b.rr = b.rhs2;
+    } else {
+      b.rr = true_residual(b);
+      r0 = chview<P64>(rhi_raw, g, RS);
+    }
+    if (!std::isfinite(b.rr)) throw Error{DWF_ERR_NAN, "non-finite residual at batched CG start"};
+    b.rr_max = b.rr_true = b.rr;
+    if (b.rr <= b.target || b.cap <= 0) continue;
+    b.active = true;
+    DWF_CHECK_LAUNCH((launch_ilv_move<P64, Pi>(r0, RS, 0, H(rb, LT0), LT0, int(seg.size()), ns, RS, s)));
+    seg.push_back(k);
+  }
+  int K = int(seg.size());
+  LT = K * RS;
+  auto upload_tables = [&]() {
+    for (int r = 0; r < K; ++r) {
+      const Op<Pi>& o = *ops[seg[r]];
+      hscan[0 * K0 + r] = o.es[E_AINV];
+      hscan[1 * K0 + r] = o.es[E_AINVDAG];
+      hscan[2 * K0 + r] = o.es[E_AINVDAG_FDAG];
+    }
+    DWF_CHECK_HIP(hipMemcpyAsync(dscan, hscan, nscan * sizeof(FifthScan<R>), hipMemcpyHostToDevice, s));
+  };
+  int cur = 0;
+  XFlush<Pi> pend;
+  auto upload_coef = [&](const std::vector<double>& beta) {
+    for (int r = 0; r < K; ++r) {
+      hcoef[r] = beta[r];
+      hcoef[K + r] = sys[seg[r]]->rr;
+    }
+    DWF_CHECK_HIP(hipMemcpyAsync(dcoef, hcoef, size_t(2) * K * sizeof(double), hipMemcpyHostToDevice, s));
+  };
+  auto p_update = [&](const std::vector<double>& beta) {
+    upload_coef(beta);
+    const int nxt = (cur + 1) % KX;
+    DWF_CHECK_LAUNCH(launch_ilv_pupdate<Pi>(cv(H(rb, LT)), cv(H(pb[cur], LT)), H(pb[nxt], LT), dcoef, sc, ns, LT, RS, s));
+    cur = nxt;
+  };
+  auto flush = [&]() {
+    DWF_CHECK_LAUNCH((launch_ilv_xflush<Pi, PX>(HX(xlb, LT), pend, sc, ns, LT, RS, s)));
+    pend.n = 0;
+  };
+  if (K > 0) {
+    upload_tables();
+    p_update(std::vector<double>(K, 0.0));
+  }
+  auto launch = [&](const HopArgs<Pi>& a, bool dag) {
+    long mark = -1;
+    if (ctx->timer.on) {
+      const int epi = a.epi_scan ? (a.out2.data ? 3 : 2) : 0;
+      const LaunchCfg c = cfg_for(LT);
+      mark = timer_begin(ctx, std::string("hop_ilv_kernel<") + prec_tag(Pi::ID) + ", " + (dag ? "true" : "false") +
+                                  ", " + std::to_string(epi) + ", " + (c.ll ? "true" : "false") + ", " +
+                                  (a.cg_r.data ? "true" : "false") + ", " + std::to_string(RS) + ">");
+    }
+    DWF_CHECK_LAUNCH(launch_hop_ilv<Pi>(a, dag, RS, cfg_for(LT), s));
+    if (mark >= 0) {
+      const double fb = spinor_site_bytes<Pi>();
+      const bool xin = a.x.data != nullptr;
+      const double nb = a.cg_r.data ? 3 + (xin ? 1 : 0) : 2 + (xin ? 1 : 0) + (a.out2.data ? 1 : 0);
+      timer_end(ctx, mark, double(ns) * LT * fb * nb + double(ns) * 72 * sizeof(SS));
+    }
+  };
+  while (K > 0) {
+    const LaunchCfg cfg = cfg_for(LT);
+    const int nb = int((ns + cfg.spb - 1) / cfg.spb);
+    HopArgs<Pi> a = HopArgs<Pi>();  // value-initialized: every optional operand absent
+    a.x = CHalf<Pi>{nullptr, nullptr};
+    a.ax = R(0);
+    a.norm_partials = nullptr;
+    a.es = FifthScan<R>();
+    a.es2 = FifthScan<R>();
+    a.nsites = ns;
+    a.Ls = LT;
+    a.pb = R(1);
+    a.pc = R(0);
+    a.pm = R(0);
+    a.E = nullptr;
+    a.part_stride = pstride;
+    auto base = [&](HopArgs<Pi>& h, int out_par) {
+      h = a;
+      h.links = links + (out_par ? size_t(ns) * 72 : 0);
+      h.nbr = g->d_nbr[out_par];
+      h.order = g->d_order[out_par];
+    };
+    const Half<Pi> p = H(pb[cur], LT), r = H(rb, LT), q = H(qb, LT), te = H(teb, LT), to = H(tob, LT);
+    HopArgs<Pi> h0, h1, h2, h3;
+    base(h0, 0);  // te = A^-1 H_eo p
+    h0.in = cv(p);
+    h0.out = te;
+    h0.scale = R(1);
+    h0.epi_scan = 1;
+    h0.es_tab = dscan;
+    base(h1, 1);  // q = p - 1/4 A^-1 H_oe te, |q|^2, and to = A^-dag q
+    h1.in = cv(te);
+    h1.out = q;
+    h1.scale = R(-0.25);
+    h1.epi_scan = 1;
+    h1.es_tab = dscan;
+    h1.x = cv(p);
+    h1.ax = R(1);
+    h1.norm_partials = part;
+    h1.out2 = to;
+    h1.es2_tab = dscan + K0;
+    base(h2, 0);  // te = A^-dag H^dag_eo to
+    h2.in = cv(to);
+    h2.out = te;
+    h2.scale = R(1);
+    h2.epi_scan = 1;
+    h2.es_tab = dscan + 2 * K0;
+    base(h3, 1);  // r -= alpha (q - 1/4 H^dag_oe te), |r|^2
+    h3.in = cv(te);
+    h3.out = Half<Pi>{nullptr, nullptr};
+    h3.scale = R(-0.25);
+    h3.x = cv(q);
+    h3.ax = R(1);
+    h3.norm_partials = part;
+    h3.cg_r = r;
+    h3.cg_scalars = sc;
+    // every operand of the four stages is one of the iteration's own buffers (or absent)
+    for (const HopArgs<Pi>* h : {&h0, &h1, &h2, &h3}) {
+      const void* bufs[] = {p.data, te.data, to.data, q.data, r.data};
+      auto known = [&](const void* v, bool may_be_null) {
+        if (!v) return may_be_null;
+        for (const void* b : bufs)
+          if (v == b) return true;
+        return false;
+      };
+      if (!known(h->in.data, false) || !known(h->out.data, true) || !known(h->x.data, true) ||
+          !known(h->out2.data, true) || !known(h->cg_r.data, true) || (h->norm_partials && h->norm_partials != part))
+        throw Error{DWF_ERR_ARG, "internal: an interleaved hop operand is not one of the iteration's buffers"};
+    }
+    launch(h0, false);
+    launch(h1, false);
+    for (int k = 0; k < K; ++k)
+      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, nb, 1, sc + size_t(k) * S_COUNT, S_QQ, 1, s, pend.n));
+    pend.p[pend.n] = cv(p);
+    pend.slot[pend.n] = pend.n;
+    ++pend.n;
+    launch(h2, true);
+    launch(h3, true);
+    for (int k = 0; k < K; ++k)
+      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, nb, 1, sc + size_t(k) * S_COUNT, S_RRNEW, 0, s));
+    if (pend.n == KX) flush();
+    DWF_CHECK_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * size_t(K) * S_COUNT, hipMemcpyDeviceToHost, s));
+    DWF_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<double> rr_new(K), beta(K, 0.0);
+    std::vector<int> ru, restart(K, 0), keep(K, 1);
+    for (int r2 = 0; r2 < K; ++r2) {
+      BatchSys& b = *sys[seg[r2]];
+      b.st.iters++;
+      rr_new[r2] = hsc[size_t(r2) * S_COUNT + S_RRNEW];
+      if (!std::isfinite(rr_new[r2])) throw Error{DWF_ERR_NAN, "non-finite residual in batched CG"};
+      if (MIXED && (rr_new[r2] < delta * delta * b.rr_max || rr_new[r2] <= b.target || rr_new[r2] > 1e4 * b.rr_true))
+        ru.push_back(r2);
+    }
+    if (!ru.empty()) {
+      // reliable updates: fold the increments into the FP64 solutions, recompute the residuals
+      flush();
+      for (int r2 : ru) {
+        BatchSys& b = *sys[seg[r2]];
+        const bool diverging = rr_new[r2] > 1e4 * b.rr_true;
+        DWF_CHECK_LAUNCH(launch_ilv_accumulate<PX>(b.x, HX(xlb, LT), LT, r2, ns, RS, s));
+        rr_new[r2] = true_residual(b);
+        DWF_CHECK_LAUNCH((launch_ilv_move<P64, Pi>(chview<P64>(rhi_raw, g, RS), RS, 0, r, LT, r2, ns, RS, s)));
+        b.rr_max = b.rr_true = rr_new[r2];
+        b.st.reliable_updates++;
+        restart[r2] = rr_new[r2] > b.target && (RESTART || diverging);
+      }
+    }
+    int leaving = 0;
+    for (int r2 = 0; r2 < K; ++r2) {
+      BatchSys& b = *sys[seg[r2]];
+      if (rr_new[r2] <= b.target || b.st.iters >= b.cap) {  // converged, or out of iterations
+        b.rr = rr_new[r2];
+        b.active = false;
+        keep[r2] = 0;
+        ++leaving;
+        continue;
+      }
+      beta[r2] = restart[r2] ? 0.0 : rr_new[r2] / b.rr;
+      b.rr = rr_new[r2];
+      if (b.rr > b.rr_max) b.rr_max = b.rr;
+    }
+    if (leaving) {
+      // every increment into its FP64 solution, then the staying right-hand sides moved together
+      flush();
+      for (int r2 = 0; r2 < K; ++r2)
+        DWF_CHECK_LAUNCH(launch_ilv_accumulate<PX>(sys[seg[r2]]->x, HX(xlb, LT), LT, r2, ns, RS, s));
+      std::vector<int> nseg;
+      std::vector<double> nbeta;
+      for (int r2 = 0; r2 < K; ++r2)
+        if (keep[r2]) {
+          nseg.push_back(seg[r2]);
+          nbeta.push_back(beta[r2]);
+        }
+      const int K2 = int(nseg.size()), LT2 = K2 * RS;
+      for (int j = 0, r2 = 0; r2 < K; ++r2) {
+        if (!keep[r2]) continue;
+        DWF_CHECK_LAUNCH((launch_ilv_move<Pi, Pi>(cv(H(rb, LT)), LT, r2, H(teb, LT2), LT2, j, ns, RS, s)));
+        DWF_CHECK_LAUNCH((launch_ilv_move<Pi, Pi>(cv(H(pb[cur], LT)), LT, r2, H(tob, LT2), LT2, j, ns, RS, s)));
+        ++j;
+      }
+      std::swap(rb, teb);
+      std::swap(pb[cur], tob);
+      seg = nseg;
+      beta = nbeta;
+      K = K2;
+      LT = LT2;
+      if (K == 0) break;
+      DWF_CHECK_LAUNCH(launch_zero(xlb, half_bytes<PX>(ns, LT), s));
+      upload_tables();
+    }
+    p_update(beta);
+  }
+  if (K > 0) {
+    flush();
+    for (int r2 = 0; r2 < K; ++r2)
+      DWF_CHECK_LAUNCH(launch_ilv_accumulate<PX>(sys[seg[r2]]->x, HX(xlb, LT), LT, r2, ns, RS, s));
+  }
+  for (BatchSys* b : sys)
+    if (b->rhs2 > 0.0) b->st.last_rel = std::sqrt(b->rr / b->rhs2);
+  DWF_CHECK_HIP(hipStreamSynchronize(s));  // (the pinned mirrors are freed on return)
+}
+
+// Right-hand sides on separate fields: the single-field fused hops, one launch per lattice and
+// stage over all of them (hop_batch_kernel).
+template <typename Pi>
+static void cg_batched_fields(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double delta) {
+  constexpr bool MIXED = !std::is_same<Pi, P64>::value;
+  using PX = typename IncrementPrec<Pi>::type;
+  constexpr bool RESTART = std::is_same<Pi, PB16>::value;
+  constexpr int KX = 8;
   hipStream_t s = ctx->stream;
   const int K = int(S.size());
-  // partial sums and scalars: one stride per right-hand side
+  (void)maxit;
+  // per-system iteration state
+  struct Inner {
+    std::unique_ptr<Op<Pi>> op;
+    LaunchCfg cfg;
+    Half<Pi> r, q, te, to, fp;
+    Half<PX> xl;
+    Half<Pi> pr[KX];
+    int cur = 0;
+    XFlush<Pi> pend;
+    double* sc = nullptr;
+    double* part = nullptr;
+    int nb = 0;          // workgroups of one field in a batched hop (= partials per stage)
+    bool out2 = false;   // A^-dag q as the second output of the second hop
+    int group = 0;
+  };
+  std::vector<Inner> I(K);
   long pstride = 1024;
-  for (auto& b : S) pstride = std::max(pstride, b.g->nsites);
+  size_t hb64max = 0;
+  for (auto& b : S) {
+    pstride = std::max(pstride, long(reduction_blocks(b.g->nsites * b.p.Ls)));
+    pstride = std::max(pstride, b.g->nsites);  // (at least one site per workgroup)
+    hb64max = std::max(hb64max, half_size<P64>(b.g, b.p.Ls));
+  }
   double* part = reinterpret_cast<double*>(ws_get(ctx, "batch.partials", size_t(K) * pstride * sizeof(double)));
   double* sc = reinterpret_cast<double*>(ws_get(ctx, "batch.scalars", size_t(K) * S_COUNT * sizeof(double)));
-  std::vector<double> hsc(size_t(K) * S_COUNT);
+  double* hsc = nullptr;
+  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsc), size_t(K) * S_COUNT * sizeof(double)));
+  // pinned host and device tables of the four stages' launch arguments
+  HopArgs<Pi>* htab = nullptr;
+  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&htab), size_t(4) * K * sizeof(HopArgs<Pi>)));
+  HopArgs<Pi>* dtab = reinterpret_cast<HopArgs<Pi>*>(ws_get(ctx, "batch.table", size_t(4) * K * sizeof(HopArgs<Pi>)));
+  struct HostFree {
+    double* a;
+    HopArgs<Pi>* b;
+    ~HostFree() {
+      if (a) (void)hipHostFree(a);
+      if (b) (void)hipHostFree(b);
+    }
+  } host_free{hsc, htab};
   // FP64 temporaries shared by the reliable updates (largest system)
-  size_t hb64max = 0;
-  for (auto& b : S) hb64max = std::max(hb64max, half_size<P64>(b.g, b.p.Ls));
   void* rhi_raw = ws_get(ctx, "batch.rhi", hb64max);
   void* t64a_raw = ws_get(ctx, "batch.t64a", hb64max);
   void* t64b_raw = ws_get(ctx, "batch.t64b", hb64max);
@@ -351,20 +706,48 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
     DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, b.rhs, -1.0, rhi, b.g->nsites * Ls, Ls, s));
     return norm2_sync<P64>(ctx, cv(rhi), b.g, Ls);
   };
-  // inner vectors and start
+  const bool moebius = !(S[0].p.b == 1.0 && S[0].p.c == 0.0);
+  auto p_update = [&](int k, double beta, double rr_new) {
+    Inner& in = I[k];
+    BatchSys& b = S[k];
+    const long n5 = b.g->nsites * b.p.Ls;
+    const int nxt = (in.cur + 1) % KX;
+    const Op<Pi>& o = *in.op;
+    if (moebius) {
+      DWF_CHECK_LAUNCH(launch_cg_pupdate_f<Pi>(cv(in.r), cv(in.pr[in.cur]), in.pr[nxt], in.fp, beta, in.sc, rr_new, n5,
+                                               b.p.Ls, o.b, o.c, o.m, s));
+    } else {
+      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(cv(in.r), cv(in.pr[in.cur]), in.pr[nxt], beta, in.sc, rr_new, n5, b.p.Ls, s));
+    }
+    in.cur = nxt;
+  };
+  auto flush = [&](int k) {
+    Inner& in = I[k];
+    const long n5 = S[k].g->nsites * S[k].p.Ls;
+    DWF_CHECK_LAUNCH((launch_xflush<Pi, PX>(in.xl, in.pend, in.sc, n5, S[k].p.Ls, s)));
+    in.pend.n = 0;
+  };
+  // set up and start every system
   for (int k = 0; k < K; ++k) {
     BatchSys& b = S[k];
+    Inner& in = I[k];
     const int Ls = b.p.Ls;
     const long n5 = b.g->nsites * Ls;
     const size_t hbi = half_size<Pi>(b.g, Ls);
     const std::string t = "batch." + std::to_string(k) + ".";
-    b.r = ws_get(ctx, t + "r", hbi);
-    b.pv = ws_get(ctx, t + "p", hbi);
-    b.q = ws_get(ctx, t + "q", hbi);
-    b.Ap = ws_get(ctx, t + "Ap", hbi);
-    b.te = ws_get(ctx, t + "te", hbi);
-    b.xl = MIXED ? ws_get(ctx, t + "xlo", half_size<PX>(b.g, Ls)) : (void*)b.x.data;
-    b.E = fifth_matrices(ctx, Ls, b.p.M5, b.p.mass, b.p.b, b.p.c, Pi::ID);
+    in.op = std::make_unique<Op<Pi>>(ctx, b.g, b.p, b.Ui);
+    in.cfg = batch_config(ctx, Pi::ID, Ls);
+    in.sc = sc + size_t(k) * S_COUNT;
+    in.part = part + size_t(k) * pstride;
+    in.nb = int((b.g->nsites + in.cfg.spb - 1) / in.cfg.spb);
+    in.out2 = in.op->scan_ok && (Ls == 8 || Ls == 16 || Ls == 32);
+    in.r = hview<Pi>(ws_get(ctx, t + "r", hbi), b.g, Ls);
+    in.q = hview<Pi>(ws_get(ctx, t + "q", hbi), b.g, Ls);
+    in.te = hview<Pi>(ws_get(ctx, t + "te", hbi), b.g, Ls);
+    in.to = hview<Pi>(ws_get(ctx, t + "to", hbi), b.g, Ls);
+    in.fp = moebius ? hview<Pi>(ws_get(ctx, t + "fp", hbi), b.g, Ls) : Half<Pi>{nullptr, nullptr};
+    in.xl = hview<PX>(MIXED ? ws_get(ctx, t + "xlo", half_size<PX>(b.g, Ls)) : (void*)b.x.data, b.g, Ls);
+    for (int j = 0; j < KX; ++j) in.pr[j] = hview<Pi>(ws_get(ctx, t + "p" + std::to_string(j), hbi), b.g, Ls);
     b.rhs2 = norm2_sync<P64>(ctx, b.rhs, b.g, Ls);
     b.target = b.tol_n * b.tol_n * b.rhs2;
     b.active = b.rhs2 > 0.0;
@@ -372,160 +755,115 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
       DWF_CHECK_LAUNCH(launch_zero(b.x.data, half_size<P64>(b.g, Ls), s));
       continue;
     }
-    b.rr = true_residual(b);
+    Half<P64> rhi = hview<P64>(rhi_raw, b.g, Ls);
+    if (norm2_sync<P64>(ctx, cv(b.x), b.g, Ls) == 0.0) {
+      DWF_CHECK_HIP(hipMemcpyAsync(rhi.data, b.rhs.data, half_size<P64>(b.g, Ls), hipMemcpyDeviceToDevice, s));
+      b.rr = b.rhs2;
+    } else {
+      b.rr = true_residual(b);
+    }
     if (!std::isfinite(b.rr)) throw Error{DWF_ERR_NAN, "non-finite residual at batched CG start"};
     b.rr_max = b.rr_true = b.rr;
     if (b.rr <= b.target || b.cap <= 0) { b.active = false; continue; }
-    Half<P64> rhi = hview<P64>(rhi_raw, b.g, Ls);
-    Half<Pi> r = hview<Pi>(b.r, b.g, Ls);
-    DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), r, n5, Ls, s)));
-    if (MIXED) DWF_CHECK_LAUNCH(launch_zero(b.xl, half_size<PX>(b.g, Ls), s));
-    DWF_CHECK_LAUNCH(launch_axpby<Pi>(1.0, cv(r), 0.0, hview<Pi>(b.pv, b.g, Ls), n5, Ls, s));
-    DWF_CHECK_LAUNCH(launch_set_scalar(sc + k * S_COUNT, S_RR, b.rr, s));
-  }
-  // descriptor tables of the four hop stages, rebuilt when the active set changes
-  std::vector<MultiGroup<Pi>> hg[4];
-  std::vector<MultiRhs<Pi>> hr[4];
-  MultiGroup<Pi>* dg[4];
-  MultiRhs<Pi>* dr[4];
-  for (int st = 0; st < 4; ++st) {
-    dg[st] = reinterpret_cast<MultiGroup<Pi>*>(ws_get(ctx, "batch.dg" + std::to_string(st), sizeof(MultiGroup<Pi>) * K));
-    dr[st] = reinterpret_cast<MultiRhs<Pi>*>(ws_get(ctx, "batch.dr" + std::to_string(st), sizeof(MultiRhs<Pi>) * K));
-  }
-  const bool moebius = !(S[0].p.b == 1.0 && S[0].p.c == 0.0);
-  std::vector<int> hop_blocks(K, 0);
-  bool scan_st[4] = {false, false, false, false};  // every right-hand side of the stage has its scan form
-  // the epilogue of slot `slot` of system b in recurrence form
-  auto scan_of = [&](const BatchSys& b, int slot, FifthScan<R>& out) -> bool {
-    FifthScan<double> e;
-    if (!fifth_scan(b.p.Ls, b.p.M5, b.p.mass, b.p.b, b.p.c, slot, &e)) return false;
-    out.m = R(e.m);
-    for (int ch = 0; ch < 2; ++ch) {
-      const FifthChir<double>& q = e.ch[ch];
-      out.ch[ch] = FifthChir<R>{R(q.a1), R(q.b1), R(q.inv_alpha), R(q.a), R(q.corr), q.d1, q.d2, q.has_inv};
+    if (MIXED) {
+      DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(cv(rhi), in.r, n5, Ls, s)));
+      DWF_CHECK_LAUNCH(launch_zero(in.xl.data, half_size<PX>(b.g, Ls), s));
+    } else {
+      DWF_CHECK_HIP(hipMemcpyAsync(in.r.data, rhi.data, half_size<P64>(b.g, Ls), hipMemcpyDeviceToDevice, s));
     }
-    return true;
-  };
-  auto build_tables = [&]() {
-    // group active systems by (lattice, links): consecutive entries of one group share links
-    std::vector<int> order_k;
-    std::vector<std::pair<const Geometry*, const void*>> keys;
-    std::vector<std::vector<int>> members;
-    for (int k = 0; k < K; ++k) {
-      if (!S[k].active) continue;
-      int gi = -1;
-      for (size_t j = 0; j < keys.size(); ++j)
-        if (keys[j].first == S[k].g && keys[j].second == S[k].Ui && S[members[j][0]].p.Ls == S[k].p.Ls) gi = int(j);
-      if (gi < 0) { keys.push_back({S[k].g, S[k].Ui}); members.push_back({}); gi = int(keys.size()) - 1; }
-      members[gi].push_back(k);
+    p_update(k, 0.0, b.rr);
+  }
+  // lattices: systems on one geometry with one link field, Ls and epilogue form (the same kernel
+  // variant) share the batched launches
+  std::vector<int> group_first;
+  for (int k = 0; k < K; ++k) {
+    int gi = -1;
+    for (size_t j = 0; j < group_first.size(); ++j) {
+      const int f = group_first[j];
+      if (S[f].g == S[k].g && S[f].Ui == S[k].Ui && S[f].p.Ls == S[k].p.Ls && I[f].op->scan_ok == I[k].op->scan_ok)
+        gi = int(j);
     }
-    for (int st = 0; st < 4; ++st) {
-      hg[st].clear();
-      hr[st].clear();
-      scan_st[st] = true;
-      const int out_par = (st == 0 || st == 2) ? 0 : 1;
-      long blocks = 0;
-      for (size_t j = 0; j < keys.size(); ++j) {
-        const BatchSys& b0 = S[members[j][0]];
-        const int Ls = b0.p.Ls;
-        MultiGroup<Pi> G;
-        G.links = reinterpret_cast<const typename Pi::S*>(b0.Ui) + (out_par ? size_t(b0.g->nsites) * 72 : 0);
-        G.nbr = b0.g->d_nbr[out_par];
-        G.order = b0.g->d_order[out_par];
-        G.nsites = b0.g->nsites;
-        G.Ls = Ls;
-        int spb = std::max(1, 256 / Ls);
-        while (spb > 1 && multi_lds_bytes<Pi>(spb, Ls, true) > 65536) --spb;
-        G.spb = spb;
-        G.block_begin = blocks;
-        G.rhs_begin = int(hr[st].size());
-        G.nrhs = int(members[j].size());
-        blocks += (G.nsites + spb - 1) / spb;
-        hg[st].push_back(G);
-        for (int k : members[j]) {
-          BatchSys& b = S[k];
-          hop_blocks[k] = int((G.nsites + spb - 1) / spb);
-          const R* E = reinterpret_cast<const R*>(b.E);
-          const size_t ls2 = size_t(Ls) * Ls;
-          MultiRhs<Pi> Q;
-          Q.pb = R(b.p.b);
-          Q.pc = R(b.p.c);
-          Q.pm = R(b.p.mass);
-          Q.ax = R(0);
-          Q.x = {nullptr, nullptr};
-          Q.norm_partials = nullptr;
-          if (st == 0) {  // te = A^-1 H_eo F p
-            Q.in = chview<Pi>(b.pv, b.g, Ls); Q.out = hview<Pi>(b.te, b.g, Ls);
-            Q.E = E + size_t(E_AINV) * 2 * ls2; Q.scale = R(1);
-          } else if (st == 1) {  // q = p - 1/4 A^-1 H_oe F te, |q|^2
-            Q.in = chview<Pi>(b.te, b.g, Ls); Q.out = hview<Pi>(b.q, b.g, Ls);
-            Q.E = E + size_t(E_AINV) * 2 * ls2; Q.scale = R(-0.25);
-            Q.x = chview<Pi>(b.pv, b.g, Ls); Q.ax = R(1);
-            Q.norm_partials = part + size_t(k) * pstride;
-          } else if (st == 2) {  // te = A^-dag F^dag H^dag_eo (A^-dag q)   [A^-dag q is in Ap]
-            Q.in = chview<Pi>(b.Ap, b.g, Ls); Q.out = hview<Pi>(b.te, b.g, Ls);
-            Q.E = E + size_t(E_AINVDAG_FDAG) * 2 * ls2; Q.scale = R(1);
-          } else {  // r -= alpha (q - 1/4 F^dag H^dag_oe te), |r|^2   (M^dag q not stored)
-            Q.in = chview<Pi>(b.te, b.g, Ls); Q.out = hview<Pi>(b.Ap, b.g, Ls);
-            Q.E = moebius ? E + size_t(E_FDAG) * 2 * ls2 : nullptr; Q.scale = R(-0.25);
-            Q.x = chview<Pi>(b.q, b.g, Ls); Q.ax = R(1);
-            Q.cg_r = hview<Pi>(b.r, b.g, Ls);
-            Q.cg_sc = sc + size_t(k) * S_COUNT;
-            Q.norm_partials = part + size_t(k) * pstride;
-          }
-          if (Q.E) {
-            const int slot = int((Q.E - E) / (2 * ls2));
-            Q.scan = scan_of(b, slot, Q.es) ? 1 : 0;
-            if (!Q.scan) scan_st[st] = false;
-          }
-          hr[st].push_back(Q);
+    if (gi < 0) {
+      group_first.push_back(k);
+      gi = int(group_first.size()) - 1;
+    }
+    I[k].group = gi;
+  }
+  // one launch per lattice and stage over the systems in act (their tables at htab + stage * K)
+  std::vector<int> act;
+  auto launch_stage = [&](int stage, bool dag, bool pro) {
+    for (size_t gi = 0; gi < group_first.size(); ++gi) {
+      int first = -1, n = 0;
+      for (size_t j = 0; j < act.size(); ++j)
+        if (I[act[j]].group == int(gi)) {
+          if (first < 0) first = int(j);
+          ++n;
         }
-      }
-      if (!hg[st].empty()) {
-        DWF_CHECK_HIP(hipMemcpy(dg[st], hg[st].data(), sizeof(MultiGroup<Pi>) * hg[st].size(), hipMemcpyHostToDevice));
-        DWF_CHECK_HIP(hipMemcpy(dr[st], hr[st].data(), sizeof(MultiRhs<Pi>) * hr[st].size(), hipMemcpyHostToDevice));
-      }
+      if (n == 0) continue;
+      const int k0 = act[first];
+      const HopArgs<Pi>& a0 = htab[size_t(stage) * K + first];
+      long mark = -1;
+      if (ctx->timer.on) mark = timer_begin(ctx, I[k0].op->hop_name(a0, dag, pro, I[k0].cfg, true));
+      DWF_CHECK_LAUNCH(launch_hop<Pi>(a0, dag, pro, I[k0].cfg, s, dtab + size_t(stage) * K + first, n));
+      if (mark >= 0) timer_end(ctx, mark, double(n) * I[k0].op->hop_bytes(a0));
     }
   };
   int nactive = 0;
   for (auto& b : S) nactive += b.active ? 1 : 0;
-  if (nactive) build_tables();
   int it = 0;
-  while (nactive > 0 && it < maxit) {
-    // q = M p (one launch per stage for all right-hand sides), alpha = rr / |q|^2
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[0], hg[0], dr[0], false, moebius, true, s, scan_st[0]));
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[1], hg[1], dr[1], false, moebius, true, s, scan_st[1]));
-    for (int k = 0; k < K; ++k) {
-      if (!S[k].active) continue;
-      BatchSys& b = S[k];
-      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, hop_blocks[k], 1, sc + k * S_COUNT, S_QQ, 1, s, 0));
-      // A^-dag q into Ap (consumed by the next stage before Ap is overwritten)
-      DWF_CHECK_LAUNCH(launch_fifth<Pi>(chview<Pi>(b.q, b.g, b.p.Ls), hview<Pi>(b.Ap, b.g, b.p.Ls),
-                                        reinterpret_cast<const R*>(b.E) + size_t(E_AINVDAG) * 2 * b.p.Ls * b.p.Ls,
-                                        nullptr, CHalf<Pi>{nullptr, nullptr}, R(0), b.g->nsites, b.p.Ls, nullptr, s));
+  while (nactive > 0) {
+    // the active systems, grouped by lattice (consecutive table entries of one group)
+    act.clear();
+    for (size_t gi = 0; gi < group_first.size(); ++gi)
+      for (int k = 0; k < K; ++k)
+        if (S[k].active && I[k].group == int(gi)) act.push_back(k);
+    const int na = int(act.size());
+    for (int j = 0; j < na; ++j) {
+      const int k = act[j];
+      Inner& in = I[k];
+      const Op<Pi>& o = *in.op;
+      const Half<Pi> p = in.pr[in.cur];
+      typename Op<Pi>::CgStep cg;
+      cg.r = in.r;
+      cg.scalars = in.sc;
+      const Half<Pi> q2 = in.out2 ? in.to : Half<Pi>{nullptr, nullptr};
+      // q = M p (Moebius: from F p), |q|^2, and A^-dag q
+      htab[0 * K + j] = o.hop_args(0, cv(moebius ? in.fp : p), in.te, o.em(moebius ? E_F_AINV : E_AINV), 1.0);
+      htab[1 * K + j] = o.hop_args(1, cv(in.te), in.q, o.em(E_AINV), -0.25, cv(p), 1.0, in.part, typename Op<Pi>::CgStep(),
+                                   q2, E_AINVDAG);
+      // r -= alpha M^dag q, |r|^2
+      htab[2 * K + j] = o.hop_args(0, cv(in.to), in.te, o.em(E_AINVDAG_FDAG), 1.0);
+      htab[3 * K + j] = o.hop_args(1, cv(in.te), Half<Pi>{nullptr, nullptr}, moebius ? o.em(E_FDAG) : nullptr, -0.25,
+                                   cv(in.q), 1.0, in.part, cg);
     }
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[2], hg[2], dr[2], true, false, true, s, scan_st[2]));
-    DWF_CHECK_LAUNCH(launch_hop_multi<Pi>(dg[3], hg[3], dr[3], true, false, moebius, s, scan_st[3]));
-    for (int k = 0; k < K; ++k) {
-      if (!S[k].active) continue;
-      BatchSys& b = S[k];
-      const int Ls = b.p.Ls;
-      const long n5 = b.g->nsites * Ls;
-      // |r|^2 from the partials of the last stage; xl += alpha p (alpha kept in history slot 0)
-      DWF_CHECK_LAUNCH(launch_reduce(part + size_t(k) * pstride, hop_blocks[k], 1, sc + k * S_COUNT, S_RRNEW, 0, s));
-      XFlush<Pi> f;
-      f.p[0] = chview<Pi>(b.pv, b.g, Ls);
-      f.slot[0] = 0;
-      f.n = 1;
-      DWF_CHECK_LAUNCH((launch_xflush<Pi, PX>(hview<PX>(b.xl, b.g, Ls), f, sc + k * S_COUNT, n5, Ls, s)));
+    for (int stage = 0; stage < 4; ++stage)
+      DWF_CHECK_HIP(hipMemcpyAsync(dtab + size_t(stage) * K, htab + size_t(stage) * K, na * sizeof(HopArgs<Pi>),
+                                   hipMemcpyHostToDevice, s));
+    launch_stage(0, false, false);
+    launch_stage(1, false, false);
+    for (int k : act) {
+      Inner& in = I[k];
+      if (!in.out2)
+        in.op->fifth(cv(in.q), in.to, E_AINVDAG);  // A^-dag q (dense-epilogue extents)
+      DWF_CHECK_LAUNCH(launch_reduce(in.part, in.nb, 1, in.sc, S_QQ, 1, s, in.pend.n));
+      in.pend.p[in.pend.n] = cv(in.pr[in.cur]);
+      in.pend.slot[in.pend.n] = in.pend.n;
+      ++in.pend.n;
     }
-    DWF_CHECK_HIP(hipMemcpyAsync(hsc.data(), sc, sizeof(double) * hsc.size(), hipMemcpyDeviceToHost, s));
+    launch_stage(2, true, false);
+    launch_stage(3, true, false);
+    for (int k : act) {
+      Inner& in = I[k];
+      DWF_CHECK_LAUNCH(launch_reduce(in.part, in.nb, 1, in.sc, S_RRNEW, 0, s));
+      if (in.pend.n == KX) flush(k);
+    }
+    DWF_CHECK_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * size_t(K) * S_COUNT, hipMemcpyDeviceToHost, s));
     DWF_CHECK_HIP(hipStreamSynchronize(s));
     ++it;
     bool changed = false;
-    for (int k = 0; k < K; ++k) {
+    for (int k : act) {
       BatchSys& b = S[k];
-      if (!b.active) continue;
+      Inner& in = I[k];
       const int Ls = b.p.Ls;
       const long n5 = b.g->nsites * Ls;
       b.st.iters++;
@@ -534,40 +872,83 @@ static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double
       const bool diverging = rr_new > 1e4 * b.rr_true;
       bool restart = false;
       if (MIXED && (rr_new < delta * delta * b.rr_max || rr_new <= b.target || diverging)) {
-        DWF_CHECK_LAUNCH(launch_accumulate<PX>(b.x, hview<PX>(b.xl, b.g, Ls), n5, Ls, s));
+        // reliable update: fold the increment into the FP64 solution, recompute r in FP64
+        flush(k);
+        DWF_CHECK_LAUNCH(launch_accumulate<PX>(b.x, in.xl, n5, Ls, s));
         rr_new = true_residual(b);
-        DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(chview<P64>(rhi_raw, b.g, Ls), hview<Pi>(b.r, b.g, Ls), n5, Ls, s)));
+        DWF_CHECK_LAUNCH((launch_convert<P64, Pi>(chview<P64>(rhi_raw, b.g, Ls), in.r, n5, Ls, s)));
         b.rr_max = b.rr_true = rr_new;
         b.st.reliable_updates++;
         restart = rr_new > b.target && (RESTART || diverging);
       }
-      if (rr_new <= b.target) {
-        b.rr = rr_new;
-        b.active = false;
-        changed = true;
-        continue;
-      }
-      if (b.st.iters >= b.cap) {  // out of iterations: stop with the current iterate
+      if (rr_new <= b.target || b.st.iters >= b.cap) {  // converged, or out of iterations
         b.rr = rr_new;
         b.active = false;
         changed = true;
         continue;
       }
       const double beta = restart ? 0.0 : rr_new / b.rr;
-      DWF_CHECK_LAUNCH(launch_cg_pupdate<Pi>(chview<Pi>(b.r, b.g, Ls), chview<Pi>(b.pv, b.g, Ls),
-                                             hview<Pi>(b.pv, b.g, Ls), beta, sc + k * S_COUNT, rr_new, n5, Ls, s));
+      p_update(k, beta, rr_new);
       b.rr = rr_new;
       if (b.rr > b.rr_max) b.rr_max = b.rr;
     }
-    nactive = 0;
-    for (auto& b : S) nactive += b.active ? 1 : 0;
-    if (changed && nactive) build_tables();
+    if (changed) {
+      nactive = 0;
+      for (auto& b : S) nactive += b.active ? 1 : 0;
+    }
   }
-  for (auto& b : S) {
-    if (MIXED && b.rhs2 > 0.0)
-      DWF_CHECK_LAUNCH(launch_accumulate<PX>(b.x, hview<PX>(b.xl, b.g, b.p.Ls), b.g->nsites * b.p.Ls, b.p.Ls, s));
-    b.st.last_rel = b.rhs2 > 0 ? std::sqrt(b.rr / b.rhs2) : 0.0;
+  for (int k = 0; k < K; ++k) {
+    BatchSys& b = S[k];
+    if (b.rhs2 <= 0.0) continue;
+    if (I[k].pend.n) flush(k);
+    if (MIXED) DWF_CHECK_LAUNCH(launch_accumulate<PX>(b.x, I[k].xl, b.g->nsites * b.p.Ls, b.p.Ls, s));
+    b.st.last_rel = std::sqrt(b.rr / b.rhs2);
   }
+  DWF_CHECK_HIP(hipStreamSynchronize(s));  // (the pinned tables are freed on return)
+}
+
+// The batched CG: the right-hand sides that can be interleaved (Shamir operator, Ls 8, 16 or 32,
+// recurrence-form blocks; per lattice, at most 256 / Ls at a time) run interleaved, the others on
+// separate fields.
+template <typename Pi>
+static void cg_batched(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit, double delta) {
+  std::vector<char> done(S.size(), 0);
+  for (size_t k = 0; k < S.size(); ++k) {
+    const dwf_params& p = S[k].p;
+    const bool ok = p.b == 1.0 && p.c == 0.0 && !p.b_s && !p.c_s && (p.Ls == 8 || p.Ls == 16 || p.Ls == 32) &&
+                    !ilv_config(ctx, Pi::ID, p.Ls).off;
+    if (!ok || done[k]) continue;
+    FifthScan<double> e;
+    bool scan = true;
+    for (int slot = 0; scan && slot < E_COUNT; ++slot) scan = fifth_scan(p.Ls, p.M5, p.mass, p.b, p.c, slot, &e);
+    if (!scan) continue;
+    std::vector<BatchSys*> chunk;
+    for (size_t j = k; j < S.size() && int(chunk.size()) < 256 / p.Ls; ++j) {
+      const dwf_params& q = S[j].p;
+      if (done[j] || S[j].g != S[k].g || S[j].Ui != S[k].Ui || q.Ls != p.Ls || !(q.b == 1.0 && q.c == 0.0) || q.b_s ||
+          q.c_s)
+        continue;
+      bool sj = true;
+      for (int slot = 0; sj && slot < E_COUNT; ++slot) sj = fifth_scan(q.Ls, q.M5, q.mass, q.b, q.c, slot, &e);
+      if (!sj) continue;
+      chunk.push_back(&S[j]);
+      done[j] = 1;
+    }
+    cg_batched_ilv<Pi>(ctx, chunk, delta);
+  }
+  std::vector<BatchSys> rest;
+  std::vector<size_t> idx;
+  for (size_t k = 0; k < S.size(); ++k)
+    if (!done[k]) idx.push_back(k);
+  if (idx.empty()) return;
+  if (idx.size() == S.size()) {
+    cg_batched_fields<Pi>(ctx, S, maxit, delta);
+    return;
+  }
+  rest.reserve(idx.size());
+  for (size_t k : idx) rest.push_back(std::move(S[k]));
+  cg_batched_fields<Pi>(ctx, rest, maxit, delta);
+  for (size_t j = 0; j < idx.size(); ++j) S[idx[j]] = std::move(rest[j]);
 }
 
 // Full-system batched solve: per-RHS even-odd source preparation, the batched CG on the

@@ -127,3 +127,62 @@ def test_batch_respects_maxit(env, prec):
         assert not infos[0]["converged"]
         for x in xs:
             x.zero_()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_every_batched_shape_solves(env, ora, prec):
+    """Every shape the batched tuner may install (right-hand sides interleaved along s, or on
+    separate fields with 1..32 sites per workgroup, XCD order, links in LDS) solves a Shamir mass
+    ladder to the full-system true residual against the oracle."""
+    from paper_1111_5059_amd import autotune
+    dwf, ctx = env
+    dims, Ls = (4, 4, 2, 6), 16
+    masses = [0.01, 0.05, 0.2]
+    U = synth.random_links(dims, 0.4, 1701)
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8)
+    Ug = lat.pack_gauge(U)
+    P = dwf.PREC_NAMES[prec]
+    srcs = [synth.gaussian_spinor(dims, Ls, 1710 + k) for k in range(len(masses))]
+    pars = [lat.params(mass=m, prec_inner=P) for m in masses]
+    bs = [lat.pack(b) for b in srcs]
+    tried = set()
+    try:
+        for c in autotune.batch_candidates(P, Ls, len(masses)):
+            try:
+                autotune.install_batched(ctx, P, Ls, c)
+            except dwf.DwfError:
+                continue  # a shape the kernel cannot run is rejected before launch
+            assert autotune.current_batched(ctx, P, Ls) == c
+            tried.add(c["mode"])
+            xs = [lat.zeros(dwf.KIND_FULL) for _ in masses]
+            infos = dwf.cg_ne_batched(ctx, pars, Ug, bs, xs, tol=1e-10)
+            for k, (info, m) in enumerate(zip(infos, masses)):
+                assert info["converged"], (c, k, info)
+                po = ora.params(dims, Ls, M5=1.8, mass=m)
+                r = srcs[k] - ora.dwf(po, U, lat.unpack_np(xs[k]))
+                assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(srcs[k]), (c, k)
+    finally:
+        autotune.install_batched(ctx, P, Ls, None)
+    assert tried == {"interleaved", "separate"}
+
+
+def test_batched_tuner_installs_the_fastest_shape(env, tmp_path):
+    from paper_1111_5059_amd import autotune
+    dwf, ctx = env
+    dims, Ls = (8, 8, 8, 8), 16
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8)
+    Ug = lat.pack_gauge(synth.random_links(dims, 0.5, 1720))
+    cache = str(tmp_path / "tune.json")
+    shapes = [{"mode": "interleaved", "spb": 1, "xcd": 1, "ll": 0},
+              {"mode": "separate", "spb": 8, "xcd": 1, "ll": 1}]
+    try:
+        best, ms, table = autotune.tune_batched(lat, Ug, "fp32", [0.01, 0.02, 0.05, 0.1], iters=4,
+                                                cache=cache, shapes=shapes)
+        assert len(table) == 2 and ms == min(r["ms"] for r in table)
+        assert autotune.current_batched(ctx, "fp32", Ls) == best
+        with open(cache) as fh:
+            import json
+            assert json.load(fh)["batch|1|16|4|8x8x8x8"] == dict(best, ms=ms)
+    finally:
+        autotune.install_batched(ctx, dwf.FP32, Ls, None)
+    assert autotune.current_batched(ctx, dwf.FP32, Ls)["mode"] == "interleaved"
