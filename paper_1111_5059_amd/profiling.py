@@ -3,6 +3,7 @@
 python -m paper_1111_5059_amd.profiling stats  <run_kernel_stats.csv> <kernel-substring> [command]
 python -m paper_1111_5059_amd.profiling traffic <fetch_counter_collection.csv> <write_counter_collection.csv>
         <copy-bytes> <out.json>
+python -m paper_1111_5059_amd.profiling counters <out.md> <counter_collection.csv> [more.csv ...]
 
 ``traffic`` converts FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every hop and
 fifth-dimension kernel variant in the run into HBM bytes per launch, each scaled by what the
@@ -98,6 +99,28 @@ def copy_counter(path, counter):
     return best
 
 
+def counter_table(paths):
+    """{kernel instance: {counter: mean per dispatch}} over one or more --pmc runs (each run may
+    hold other counters of the same kernels)."""
+    acc = {}
+    for path in paths:
+        for r in _rows(path):
+            k = short_name(_col(r, "Kernel_Name"))
+            if k is None:
+                continue
+            c = _col(r, "Counter_Name")
+            acc.setdefault(k, {}).setdefault(c, []).append(float(_col(r, "Counter_Value")))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def counters_markdown(table):
+    cols = sorted({c for cs in table.values() for c in cs})
+    lines = ["| kernel | " + " | ".join(cols) + " |", "|---|" + "---|" * len(cols)]
+    for k in sorted(table):
+        lines.append(f"| `{k}` | " + " | ".join(f"{table[k].get(c, float('nan')):.4g}" for c in cols) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv):
     if argv[0] == "stats":
         for k in kernel_stats(argv[1], argv[2]):
@@ -124,6 +147,12 @@ def main(argv):
         with open(out, "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d))
+        return
+    if argv[0] == "counters":
+        table = counter_table(argv[2:])
+        with open(argv[1], "w") as fh:
+            fh.write(counters_markdown(table))
+        print(json.dumps(table))
         return
     raise SystemExit(__doc__)
 
