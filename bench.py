@@ -11,7 +11,9 @@ the timed steps the script measures, on the same GPU and stream:
   * plain CG-NE of the same system in FP16 and FP32 storage (precision alone, no MADWF);
   * the 16^3 x 32, Ls = 16 solver (FP32 with FP64 reliable updates vs FP64) and force
     (force kernel bandwidth, force-gradient step) configurations;
-  * the FP64 CPU oracle on the host cores (bounded sample, extrapolated).
+  * the FP64 CPU oracle on the host cores (bounded sample, extrapolated);
+  * last, once the solve's context is closed: 8 right-hand sides (4 masses x 2 sources) on
+    32^3 x 64, Ls = 16, one at a time and as one batched CG with its tuned launch shape.
 
 python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cfg3|cfg2|cfg1]
 """
@@ -219,7 +221,14 @@ def batched_cfg5(dwf, prec="fp32", tol=1e-10, eps=0.5):
     torch.cuda.empty_cache()
 
     ctx, lat, U64, bs = setup()
+    # the batched hop's launch shape for (precision, Ls, 8 right-hand sides, this lattice)
+    from paper_1111_5059_amd import autotune
     xs = [lat.zeros(dwf.KIND_FULL) for _ in rhs]
+    t = time.perf_counter()
+    best, best_ms, table = autotune.tune_batched(lat, U64, prec, [m for m, _ in rhs], iters=6, cache=None,
+                                                 sources=[bs[k] for _, k in rhs], solutions=xs)
+    log(f"cfg5: batched shape {best} ({best_ms:.1f} ms per iteration of 8), searched {len(table)} shapes "
+        f"in {time.perf_counter() - t:.1f} s")
     pars = [lat.params(mass=m, prec_inner=P) for m, _ in rhs]
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -234,6 +243,8 @@ def batched_cfg5(dwf, prec="fp32", tol=1e-10, eps=0.5):
             "workload": f"Shamir DWF 32^3x64 Ls=16 M5=1.8, masses {masses} x 2 Gaussian sources, random SU(3) "
                         f"links eps={eps}, {prec} iterations with FP64 reliable updates, true residual {tol:g}",
             "batched_s": t_bat, "sequential_s": t_seq, "speedup": t_seq / t_bat,
+            "tuned_shape": best, "tuned_ms_per_iteration": best_ms,
+            "shapes_searched": [dict(c) for c in table],
             "per_rhs": [{"mass": m, "source": k, "iters_sequential": a["iters"], "iters_batched": c["iters"],
                          "true_rel_resid_sequential": a["true_rel_resid"], "true_rel_resid_batched": c["true_rel_resid"],
                          "seconds_sequential": a["seconds"]}
@@ -348,22 +359,29 @@ def cpu_baseline(workload, U, fp64_iters, seconds_budget=25.0):
                             "iters": info1["iters"], "true_rel_resid": info1["true_rel_resid"]}}
 
 
-def precision_controls(dwf, ctx, lat, U64, bg, precs=("fp16", "fp32")):
+def precision_controls(dwf, ctx, lat, U64, bg, precs=("fp16", "fp32"), eo5=False):
     """Plain CG-NE on the headline system in FP16 and FP32 storage (FP32 arithmetic, FP64
     reliable updates, FP64 solution), no Moebius acceleration, to the same 1e-10 true residual:
-    what the precision alone buys, beside what MADWF buys (Table 1, Sec. 5)."""
+    what the precision alone buys, beside what MADWF buys (Table 1, Sec. 5).  eo5: the same
+    solves on the 5D even-odd Schur complement as well (keys "eo5_<prec>")."""
     import torch
     out = {}
-    for prec in precs:
-        x = lat.zeros(dwf.KIND_FULL)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        info = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10)
-        torch.cuda.synchronize()
-        out[prec] = dict(info, wall_s=time.perf_counter() - t)
-        log(f"plain {prec} CG: {out[prec]['wall_s']:.2f} s, {info['iters']} iterations, "
-            f"{info['reliable_updates']} reliable updates, resid {info['true_rel_resid']:.2e}")
-        del x
+    solvers = [("", dwf.cg_ne)] + ([("eo5_", dwf.cg_ne_5d)] if eo5 else [])
+    for tag, solve in solvers:
+        for prec in precs:
+            # this solver's workspace alone (the context's others freed), allocated before timing
+            ctx.release()
+            x = lat.zeros(dwf.KIND_FULL)
+            solve(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10, maxit=2)
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = solve(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10)
+            torch.cuda.synchronize()
+            out[tag + prec] = dict(info, wall_s=time.perf_counter() - t)
+            log(f"plain {tag}{prec} CG: {out[tag + prec]['wall_s']:.2f} s, {info['iters']} iterations, "
+                f"{info['reliable_updates']} reliable updates, resid {info['true_rel_resid']:.2e}")
+            del x
     return out
 
 
@@ -379,15 +397,17 @@ def cfg2_measure(dwf):
     U64 = lat.pack_gauge(synth.random_links(dims, 0.5, synth.link_seed(2)))
     bg = lat.pack(synth.gaussian_spinor(dims, Ls, synth.source_seed(2)))
     dwf.cg_ne(ctx, lat.params(prec_inner=dwf.FP32), U64, bg, lat.zeros(dwf.KIND_FULL), tol=1e-10, maxit=3)
+    dwf.cg_ne_5d(ctx, lat.params(prec_inner=dwf.FP32), U64, bg, lat.zeros(dwf.KIND_FULL), tol=1e-10, maxit=3)
     solves = {}
-    for prec in ("fp64", "fp32"):
-        x = lat.zeros(dwf.KIND_FULL)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        info = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10)
-        torch.cuda.synchronize()
-        solves[prec] = dict(info, wall_s=time.perf_counter() - t)
-        log(f"cfg2 {prec} CG: {solves[prec]['wall_s']:.3f} s, {info['iters']} iterations")
+    for tag, solve in (("", dwf.cg_ne), ("eo5_", dwf.cg_ne_5d)):
+        for prec in ("fp64", "fp32"):
+            x = lat.zeros(dwf.KIND_FULL)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = solve(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), U64, bg, x, tol=1e-10)
+            torch.cuda.synchronize()
+            solves[tag + prec] = dict(info, wall_s=time.perf_counter() - t)
+            log(f"cfg2 {tag}{prec} CG: {solves[tag + prec]['wall_s']:.3f} s, {info['iters']} iterations")
     hop = {prec: time_hop(dwf, ctx, lat, U64, prec, reps=50) for prec in ("fp64", "fp32", "fp16")}
     for prec, h in hop.items():
         log(f"cfg2 hop {prec}: {h['ms']:.4f} ms, {h['GBps']:.0f} GB/s")
@@ -397,6 +417,9 @@ def cfg2_measure(dwf):
                         "true residual 1e-10",
             "fp64_cg": solves["fp64"], "fp32_reliable_cg": solves["fp32"],
             "speedup_fp32_over_fp64": solves["fp64"]["wall_s"] / solves["fp32"]["wall_s"],
+            "eo5": {"fp64_cg": solves["eo5_fp64"], "fp32_reliable_cg": solves["eo5_fp32"],
+                    "time_ratio_5d_over_4d": {p: solves["eo5_" + p]["wall_s"] / solves[p]["wall_s"]
+                                              for p in ("fp64", "fp32")}},
             "dslash": {k: {"GBps": v["GBps"], "pct_hbm_peak": 100 * v["GBps"] / HBM_PEAK_GBS, "GFLOPs": v["GFLOPs"],
                            "ms": v["ms"]} for k, v in hop.items()}}
 
@@ -508,6 +531,8 @@ def main():
     ap.add_argument("--batched-cfg5", action="store_true",
                     help="only the 8-right-hand-side batched solve on 32^3x64, Ls=16 (about 180 GB of HBM; "
                          "prints its own JSON line)")
+    ap.add_argument("--no-cfg5", action="store_true",
+                    help="skip the 8-right-hand-side batched solve that otherwise ends the run")
     ap.add_argument("--madwf-scan", action="store_true",
                     help="only the Figure-1 Moebius-tolerance scan on 32^3x8, Ls=32 (prints its own JSON line)")
     args = ap.parse_args()
@@ -635,7 +660,7 @@ def main():
 
     controls = None
     if not args.no_extras:
-        controls = precision_controls(dwf, ctx, lat, U64, bg)
+        controls = precision_controls(dwf, ctx, lat, U64, bg, eo5=True)
 
     cfg2 = cfg4 = None
     if not args.no_extras and args.workload == "cfg3":
@@ -660,6 +685,14 @@ def main():
                 "launches_per_step": d["launches"] / max(1, args.steps), "bytes_per_launch": bpl,
                 "avg_launch_ms": avg_ms, "share_of_step": d["ms"] * 1e-3 / elapsed}
         log(f"dominant kernel {dom}: {d['launches']} launches, {avg_ms:.3f} ms avg, {achieved:.0f} GB/s")
+    # ---- batched right-hand sides (32^3 x 64, Ls = 16): its own contexts, after this one is gone
+    cfg5 = None
+    if not args.no_extras and not args.no_cfg5 and args.workload == "cfg3":
+        del xg, bg, U64, lat, inner
+        ctx.close()
+        torch.cuda.empty_cache()
+        cfg5 = batched_cfg5(dwf)
+        log(f"cfg5: batched {cfg5['batched_s']:.2f} s against {cfg5['sequential_s']:.2f} s one at a time")
     out = {
         "metric": METRIC,
         "value": sec,
@@ -694,6 +727,7 @@ def main():
         "cpu_baseline": cpu,
         "cfg2_solver": cfg2,
         "cfg4_force": cfg4,
+        "cfg5_batched": cfg5,
         "hasenbusch_ladder": ladder,
         "fgi_trajectory": fgi,
         "s_dependent_moebius": sdep,

@@ -71,6 +71,10 @@ enum dwf_op {
   DWF_OP_A = 3,     /* site-local A on a half field */
   DWF_OP_AINV = 4   /* site-local A^-1 on a half field */
 };
+enum dwf_op5 {
+  DWF_OP5_HOP = 0,  /* K = (5 - M5) - D(m), both 5D parities (dwf_dslash_5d) */
+  DWF_OP5_SCHUR = 1 /* S = d0 - K_eo K_oe / d0 on the even 5D parity (dwf_dslash_5d) */
+};
 
 typedef struct {
   int dims[4];    /* X, Y, Z, T: each even and >= 2 */
@@ -129,6 +133,11 @@ typedef struct dwf_ctx dwf_ctx;
 int dwf_ctx_create(dwf_ctx** ctx, void* stream);
 int dwf_ctx_destroy(dwf_ctx* ctx);
 int dwf_ctx_set_stream(dwf_ctx* ctx, void* stream);
+/* Free the context's solver workspace (after the work queued on its stream); the geometry
+ * tables, fifth-dimension tables and tuned shapes stay.  The next call allocates what it
+ * needs again.  For callers that switch between solvers whose workspaces do not fit in
+ * device memory together. */
+int dwf_ctx_release(dwf_ctx* ctx);
 const char* dwf_last_error(void);
 
 /* Bytes of a packed field of the given kind and precision (0 on bad arguments). */
@@ -181,11 +190,38 @@ int dwf_dslash_noalloc(dwf_ctx* ctx, const dwf_params* p, const void* U, const v
  * iterations about 40 GB). */
 int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info);
 
+/* Shamir DWF checkerboarded in five dimensions (an alternative to the 4D even-odd
+ * split above; Sec. 4 admits any solver of D_DW(m) inside MADWF).  With the 5D parity
+ * (x + y + z + t + s) mod 2 and d0 = 5 - M5, D(m) = d0 - K, where
+ *   K psi = 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)]
+ *           + P- psi_{s+1} + P+ psi_{s-1}       (psi_{Ls} = -m psi_0, psi_{-1} = -m psi_{Ls-1})
+ * connects opposite 5D parities only, and the even-site Schur complement is
+ * S = d0 - K_eo K_oe / d0.  Shamir only (b = 1, c = 0, no b_s / c_s; the c D_W term of a
+ * Moebius operator hops x and s together) and Ls in {2, 4, 8, 16, 32, 64, 128}; otherwise
+ * DWF_ERR_ARG.
+ *
+ * cg_ne_5d: solve D(m) x = b by CG on S^+ S x_e = S^+ (b_e + K_eo b_o / d0), then
+ * x_o = (b_o + K_oe x_e) / d0, to the full-system true residual info->tol (computed with the
+ * 4D even-odd D(m) of cg_ne).  Arguments, precisions, reliable updates, info and errors as
+ * cg_ne; x holds the initial guess.  Workspace (held by ctx): the fields of cg_ne's iteration,
+ * each one 5D-parity field (the size of one packed half), plus eight FP64 5D-parity fields.
+ *
+ * dwf_dslash_5d: one application of op on packed full fields of precision p->prec (U packed
+ * in p->prec): DWF_OP5_HOP out = K in (dagger: K^+ in); DWF_OP5_SCHUR: the even-5D-parity part
+ * of out = S in_even (dagger: S^+), its odd part zero (in's odd part is not read).  in and out
+ * must not alias. */
+int cg_ne_5d(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info);
+int dwf_dslash_5d(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op, int dagger);
+
 /* Several right-hand sides solved together (the Hasenbusch mass ladder of Sec. 3):
  * every hop stage of M_prec and M_prec^+ is ONE launch over all unconverged
  * right-hand sides, each workgroup loading the links of its sites once for all
- * right-hand sides on that lattice; one device-to-host copy per iteration
- * returns every residual.  per_rhs[k] may differ in mass, and -- a ragged batch
+ * right-hand sides on that lattice.  Shamir right-hand sides of one lattice with
+ * Ls 8, 16 or 32 run interleaved along the fifth dimension (up to 256 / Ls of them
+ * per launch: slice s of right-hand side r is slice r Ls + s of one field; tuning
+ * kernel 2); the others run as separate fields in one launch (tuning kernel 1).
+ * One device-to-host copy per iteration returns every residual.  per_rhs[k] may
+ * differ in mass, and -- a ragged batch
  * -- in extents and Ls, with U[k] the packed FP64 links of that lattice (equal
  * pointers share link loads).  All entries share M5, b, c, tbc and prec_inner.
  * b[k], x[k]: packed FP64 full fields (x[k] = initial guess on entry).

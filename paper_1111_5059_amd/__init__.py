@@ -21,6 +21,7 @@ DWF_ERR_ARG, DWF_ERR_HIP, DWF_ERR_NOMEM, DWF_ERR_NAN = -1, -2, -3, -4
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 KIND_GAUGE, KIND_FULL, KIND_EVEN, KIND_ODD = 0, 1, 2, 3
 OP_HOP, OP_MPREC, OP_FULL, OP_A, OP_AINV = 0, 1, 2, 3, 4
+OP5_HOP, OP5_SCHUR = 0, 1  # dwf_dslash_5d: K, and the even-site Schur complement S
 PREC_NAMES = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 
 
@@ -84,6 +85,7 @@ SIGNATURES = {
     "dwf_ctx_create": ([ctypes.POINTER(_vp), _vp], _ci),
     "dwf_ctx_destroy": ([_vp], _ci),
     "dwf_ctx_set_stream": ([_vp, _vp], _ci),
+    "dwf_ctx_release": ([_vp], _ci),
     "dwf_last_error": ([], ctypes.c_char_p),
     "dwf_field_bytes": ([_PP, _ci, _ci], ctypes.c_size_t),
     "dwf_pack": ([_vp, _PP, _ci, _ci, _vp, _vp], _ci),
@@ -93,6 +95,8 @@ SIGNATURES = {
     "mobius_dslash": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
     "dwf_dslash_noalloc": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci, _ci], _ci),
     "cg_ne": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)], _ci),
+    "cg_ne_5d": ([_vp, _PP, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)], _ci),
+    "dwf_dslash_5d": ([_vp, _PP, _vp, _vp, _vp, _ci, _ci], _ci),
     "cg_ne_batched": ([_vp, _ci, _PP, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                        ctypes.POINTER(SolveInfo)], _ci),
     "mobius_accel_solve": ([_vp, _PP, _PP, _vp, _vp, _vp, ctypes.POINTER(MadwfInfo)], _ci),
@@ -170,6 +174,10 @@ class Context:
         self.handle = _vp()
         _check(lib().dwf_ctx_create(ctypes.byref(self.handle), _vp(stream)))
 
+    def release(self):
+        """Free the solver workspace (dwf_ctx_release); geometry and tuned shapes stay."""
+        _check(lib().dwf_ctx_release(self.handle))
+
     def close(self):
         if self.handle:
             lib().dwf_ctx_destroy(self.handle)
@@ -227,6 +235,22 @@ def cg_ne(ctx, p, U, b, x, tol=1e-10, delta=0.1, maxit=100000):
     d = info.as_dict()
     d["converged"] = rc == DWF_OK
     return d
+
+
+def cg_ne_5d(ctx, p, U, b, x, tol=1e-10, delta=0.1, maxit=100000):
+    """cg_ne on the 5D even-odd Schur complement (Shamir DWF only)."""
+    info = SolveInfo()
+    info.tol, info.delta, info.maxit = float(tol), float(delta), int(maxit)
+    rc = _check(lib().cg_ne_5d(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(b)), _vp(_ptr(x)),
+                               ctypes.byref(info)), allow_not_converged=True)
+    d = info.as_dict()
+    d["converged"] = rc == DWF_OK
+    return d
+
+
+def dwf_dslash_5d(ctx, p, U, src, dst, op, dagger=False):
+    _check(lib().dwf_dslash_5d(ctx.handle, ctypes.byref(p), _vp(_ptr(U)), _vp(_ptr(src)), _vp(_ptr(dst)), int(op),
+                               int(bool(dagger))))
 
 
 def cg_ne_batched(ctx, per_rhs, U, bs, xs, tol=1e-10, delta=0.1, maxit=100000):

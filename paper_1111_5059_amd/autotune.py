@@ -217,40 +217,56 @@ def _batch_key(prec, Ls, nrhs, dims):
     return f"batch|{prec}|{Ls}|{nrhs}|{'x'.join(str(d) for d in dims)}"
 
 
-def tune_batched(lattice, U64, prec, masses, iters=10, cache=DEFAULT_CACHE, shapes=None, verbose=False):
-    """Time ``iters`` iterations of the batched CG of len(masses) right-hand sides (Gaussian
-    sources, zero guesses) for every shape; installs the fastest and returns (shape, ms per
-    iteration, table)."""
+def tune_batched(lattice, U64, prec, masses, iters=10, cache=DEFAULT_CACHE, shapes=None, verbose=False,
+                 sources=None, solutions=None):
+    """Time ``iters`` iterations of the batched CG of len(masses) right-hand sides (zero guesses)
+    for every shape; installs the fastest and returns (shape, ms per iteration, table).  sources /
+    solutions: the caller's full-lattice FP64 fields (one per mass; the solutions are zeroed on
+    return), so that a search at the largest sizes allocates nothing beside the solver's own
+    workspace; by default one seeded Gaussian source and fresh solution fields."""
     import time
     import torch
     P = PREC_NAMES.get(prec, prec)
     ctx, Ls, n = lattice.ctx, lattice.Ls, len(masses)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(17)
-    b = lattice.empty(KIND_FULL)
-    b.view(torch.float64).normal_(generator=g)
+    bs = sources
+    if bs is None:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(17)
+        b = lattice.empty(KIND_FULL)
+        b.view(torch.float64).normal_(generator=g)
+        bs = [b] * n
+    xs = solutions if solutions is not None else [lattice.zeros(KIND_FULL) for _ in range(n)]
+    if len(bs) != n or len(xs) != n:
+        raise ValueError("one source and one solution field per mass")
     pars = [lattice.params(mass=m, prec_inner=P) for m in masses]
-    table, best = [], None
+    table, best, mode = [], None, None
     for c in shapes or batch_candidates(P, Ls, n):
         try:
             install_batched(ctx, P, Ls, c)
         except DwfError:
             continue
-        xs = [lattice.zeros(KIND_FULL) for _ in range(n)]
-        cg_ne_batched(ctx, pars, U64, [b] * n, xs, tol=1e-14, maxit=2)  # allocations
+        if mode is not None and c["mode"] != mode:
+            ctx.release()  # the two modes' workspaces need not fit together
+        mode = c["mode"]
+        for x in xs:
+            x.zero_()
+        cg_ne_batched(ctx, pars, U64, bs, xs, tol=1e-14, maxit=2)  # workspace
         for x in xs:
             x.zero_()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        cg_ne_batched(ctx, pars, U64, [b] * n, xs, tol=1e-14, maxit=iters)
+        cg_ne_batched(ctx, pars, U64, bs, xs, tol=1e-14, maxit=iters)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / iters
-        del xs
         table.append(dict(c, ms=ms))
         if verbose:
             print(f"batch tune {prec} Ls={Ls} nrhs={n} {c}: {ms:.3f} ms per iteration", flush=True)
         if best is None or ms < best[1]:
             best = (c, ms)
+    for x in xs:
+        x.zero_()
+    if best[0]["mode"] != mode:
+        ctx.release()
     install_batched(ctx, P, Ls, best[0])
     if cache:
         save(cache, _batch_key(P, Ls, n, lattice.dims), dict(best[0], ms=best[1]))

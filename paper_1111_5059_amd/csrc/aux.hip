@@ -354,6 +354,51 @@ int launch_slice_copy(CHalf<P64> in, int Ls_in, int s_in, Half<P64> out, int Ls_
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// 4D even-odd field halves <-> 5D-parity fields.  Slice s of 4D parity q belongs to the 5D
+// parity (s + q) mod 2, where it is slot s / 2 of half q: element ((q nsites + x) 12 + k) Ls/2 + s/2
+// (FP16 norm: (q nsites + x) Ls/2 + s/2).  Thread per element of the 4D fields (grid-stride).
+template <typename P>
+__global__ void __launch_bounds__(256) eo5_split_kernel(Half<P> h0, Half<P> h1, Half<P> f5e, Half<P> f5o, long nsites,
+                                                        int Ls, int merge) {
+  const long per = nsites * 12 * Ls;
+  const int LH = Ls / 2;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * per; i += (long)gridDim.x * blockDim.x) {
+    const int q = i >= per ? 1 : 0;
+    const long r = i - q * per;
+    const long xk = r / Ls;  // x_cb * 12 + k
+    const int s = int(r - xk * Ls);
+    const Half<P> h = q ? h1 : h0;
+    const Half<P> f5 = ((s + q) & 1) ? f5o : f5e;
+    const long j5 = (q * nsites * 12 + xk) * LH + (s >> 1);
+    if (merge) h.data[r] = f5.data[j5];
+    else f5.data[j5] = h.data[r];
+    if constexpr (P::NORM) {
+      const long x = xk / 12;
+      if (xk - x * 12 == 0) {
+        const long n4 = x * Ls + s, n5 = (q * nsites + x) * LH + (s >> 1);
+        if (merge) h.norm[n4] = f5.norm[n5];
+        else f5.norm[n5] = h.norm[n4];
+      }
+    }
+  }
+}
+
+template <typename P>
+int launch_eo5_split(Half<P> h0, Half<P> h1, Half<P> f5_even, Half<P> f5_odd, long nsites, int Ls, int merge,
+                     hipStream_t st) {
+  if (Ls < 2 || Ls % 2 || nsites <= 0) return -1;
+  const long n = 2 * nsites * 12 * Ls;
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((eo5_split_kernel<P>), dim3((unsigned)blocks), dim3(256), 0, st, h0, h1, f5_even, f5_odd, nsites,
+                     Ls, merge);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+template int launch_eo5_split<P64>(Half<P64>, Half<P64>, Half<P64>, Half<P64>, long, int, int, hipStream_t);
+template int launch_eo5_split<P32>(Half<P32>, Half<P32>, Half<P32>, Half<P32>, long, int, int, hipStream_t);
+template int launch_eo5_split<P16>(Half<P16>, Half<P16>, Half<P16>, Half<P16>, long, int, int, hipStream_t);
+template int launch_eo5_split<PB16>(Half<PB16>, Half<PB16>, Half<PB16>, Half<PB16>, long, int, int, hipStream_t);
+
 // hi += lo ; lo = 0
 template <typename Px>
 __global__ void __launch_bounds__(256) accumulate_kernel(Half<P64> hi, Half<Px> lo, long n5, int Ls) {

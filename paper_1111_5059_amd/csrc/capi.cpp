@@ -208,6 +208,16 @@ int dwf_ctx_destroy(dwf_ctx* ctx) {
   });
 }
 
+int dwf_ctx_release(dwf_ctx* ctx) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  return guarded([&]() {
+    DWF_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& kv : ctx->ws) DWF_CHECK_HIP(hipFree(kv.second.first));
+    ctx->ws.clear();
+    return DWF_OK;
+  });
+}
+
 int dwf_ctx_set_stream(dwf_ctx* ctx, void* stream) {
   if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
   ctx->stream = reinterpret_cast<hipStream_t>(stream);
@@ -349,6 +359,32 @@ int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void*
     if (st != 0) set_error("cg_ne: iteration cap reached before the true residual met tol");
     return st == 0 ? DWF_OK : DWF_NOT_CONVERGED;
   });
+}
+
+int cg_ne_5d(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  int rc = check_params(p, true);
+  if (rc) return rc;
+  if (!U || !b || !x || !info) return fail(DWF_ERR_ARG, "NULL pointer");
+  if (b == x) return fail(DWF_ERR_ARG, "b and x must not alias");
+  if (!(info->tol > 0.0)) return fail(DWF_ERR_ARG, "tol must be positive");
+  return guarded([&]() {
+    const double delta = info->delta > 0 ? info->delta : 0.1;
+    const int maxit = info->maxit > 0 ? info->maxit : 100000;
+    const int st = solve_full_5d(ctx, *p, U, b, x, info->tol, maxit, delta, "cg5", info);
+    if (st != 0) set_error("cg_ne_5d: iteration cap reached before the true residual met tol");
+    return st == 0 ? DWF_OK : DWF_NOT_CONVERGED;
+  });
+}
+
+int dwf_dslash_5d(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* in, void* out, int op, int dagger) {
+  if (!ctx) return fail(DWF_ERR_ARG, "ctx is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!U || !in || !out) return fail(DWF_ERR_ARG, "NULL field pointer");
+  if (in == out) return fail(DWF_ERR_ARG, "in and out must not alias");
+  if (op != DWF_OP5_HOP && op != DWF_OP5_SCHUR) return fail(DWF_ERR_ARG, "unknown op");
+  return guarded([&]() { return dslash_5d(ctx, *p, U, in, out, op, dagger); });
 }
 
 int cg_ne_batched(dwf_ctx* ctx, int nrhs, const dwf_params* per_rhs, const void* const* U, const void* const* b,

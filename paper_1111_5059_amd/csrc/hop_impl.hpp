@@ -404,7 +404,49 @@ constexpr int hop_min_waves() { return std::is_same<P, P16>::value && NS == 1 ? 
 // RS > 0: the field holds Ls / RS right-hand sides of fifth-dimension extent RS interleaved along
 // s (slice s of right-hand side r is slice r RS + s), each with its own epilogue coefficients,
 // CG scalars and norm partials (see HopArgs).
-template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST, int RS = 0>
+// The fifth-dimension hop of the Shamir operator on 5D-checkerboarded fields, added to acc:
+//   r5 (P- psi_{s+1} + P+ psi_{s-1})   (dagger: r5 (P- psi_{s-1} + P+ psi_{s+1})),
+// psi_{Ls} = -m psi_0, psi_{-1} = -m psi_{Ls-1}, psi = a.loc at this 4D site.  The lane's output
+// slice is s = 2 j + sigma and loc's slot j' holds s' = 2 j' + 1 - sigma, so one chirality comes
+// from the lane's own slot and the other from the next lane of the site's segment (j - 1 for
+// sigma = 0, j + 1 for sigma = 1, wrapping round the segment with the factor -m).  All lanes of
+// the wave take part in the shuffle; a site's lanes are active or inactive together.
+template <typename P, bool DAG>
+__device__ __forceinline__ void eo5_fifth_hop(const HopArgs<P>& a, typename P::R r5, long x, int j, int LH,
+                                              bool active, cx<typename P::R> acc[12]) {
+  using R = typename P::R;
+  cx<R> v[12];
+  if (active) {
+    load_spinor<P>(a.loc, x, j, LH, v);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = {R(0), R(0)};
+  }
+  const int sigma = a.sigma;
+  // the neighbouring lane supplies P- (spins 2, 3) or P+ (spins 0, 1)
+  const bool nbr_minus = (sigma != 0) != DAG;
+  const bool wrap = sigma ? (j == LH - 1) : (j == 0);
+  const int jn = sigma ? (wrap ? 0 : j + 1) : (wrap ? LH - 1 : j - 1);
+  const int src = int(threadIdx.x & 63) - j + jn;
+  const R fn = wrap ? -a.pm * r5 : r5;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const cx<R> t = nbr_minus ? v[6 + k] : v[k];
+    cx<R> w;
+    w.re = __shfl(t.re, src, 64);
+    w.im = __shfl(t.im, src, 64);
+    if (nbr_minus) {
+      acc[6 + k] = acc[6 + k] + fn * w;
+      acc[k] = acc[k] + r5 * v[k];
+    } else {
+      acc[k] = acc[k] + fn * w;
+      acc[6 + k] = acc[6 + k] + r5 * v[6 + k];
+    }
+  }
+}
+
+template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST, int RS = 0,
+          bool EO5 = false>
 __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pidx, int spb) {
   using R = typename P::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -516,6 +558,11 @@ __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pid
     for (int j = 0; j < NS; ++j)
 #pragma unroll
       for (int k = 0; k < 12; ++k) acc[j][k] = a.scale * acc[j][k];
+  }
+  if constexpr (EO5) {
+    // (placed after the gathers: before them it raises the register count further)
+    static_assert(NS == 1 && !PRO && EPI == 0 && RS == 0 && !ST, "5D even-odd hop: one slice per lane, no matrices");
+    eo5_fifth_hop<P, DAG>(a, a.r5, x, s0, Ls, active, acc[0]);
   }
   // the lane's right-hand side and slice within it (interleaved fields)
   const int rhs = RS > 0 ? s0 / (RS > 0 ? RS : 1) : 0;
@@ -707,6 +754,44 @@ int launch_hop_ilv(const HopArgs<P>& a, bool dagger, int rs, const LaunchCfg& cf
   }
 }
 
+// 5D even-odd hop: workgroup pairs (2t, 2t + 1) take block t of output halves 0 and 1, the two
+// 4D parities of one traversal tile, dispatched together (and with the XCD-aware order on one
+// XCD), so that each input half read as neighbours by one is read as loc by the other while it
+// is in that XCD's L2.
+// (no occupancy floor: with the fifth-dimension hop's operand the FP16 body spills at 4 waves
+// per SIMD)
+template <typename P, int LS, bool DAG, bool LL, bool CG>
+__global__ void __launch_bounds__(256)
+    hop_eo5_kernel(HopArgs<P> a0, HopArgs<P> a1, int spb, int xcd) {
+  const long b = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+  // (one body per half: the arguments stay in the kernel-argument segment, no private copy)
+  if (b & 1) hop_body<P, LS, 1, DAG, false, 0, LL, CG, false, 0, true>(a1, b >> 1, blockIdx.x, spb);
+  else hop_body<P, LS, 1, DAG, false, 0, LL, CG, false, 0, true>(a0, b >> 1, blockIdx.x, spb);
+}
+
+template <typename P, int LS, bool DAG, bool CG>
+static int launch_eo5_t(const HopArgs<P>& a0, const HopArgs<P>& a1, const LaunchCfg& cfg, hipStream_t st) {
+  const int threads = cfg.spb * a0.Ls;
+  const long blocks = 2 * ((a0.nsites + cfg.spb - 1) / cfg.spb);
+  const size_t lds = hop_lds_bytes<P>(cfg, a0.Ls, false);
+  if (cfg.ll)
+    hipLaunchKernelGGL((hop_eo5_kernel<P, LS, DAG, true, CG>), dim3((unsigned)blocks), dim3(threads), lds, st, a0, a1,
+                       cfg.spb, cfg.xcd);
+  else
+    hipLaunchKernelGGL((hop_eo5_kernel<P, LS, DAG, false, CG>), dim3((unsigned)blocks), dim3(threads), lds, st, a0,
+                       a1, cfg.spb, cfg.xcd);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename P, int LS>
+int launch_hop_eo5_ls(const HopArgs<P>& a0, const HopArgs<P>& a1, bool dag, const LaunchCfg& cfg, hipStream_t st) {
+  if (dag) {
+    if (a0.cg_r.data) return launch_eo5_t<P, LS, true, true>(a0, a1, cfg, st);
+    return launch_eo5_t<P, LS, true, false>(a0, a1, cfg, st);
+  }
+  return launch_eo5_t<P, LS, false, false>(a0, a1, cfg, st);
+}
+
 // the staged variant applies to this instantiation and launch shape
 template <typename P, int LS, int NS, bool PRO, int EPI>
 constexpr bool stage_capable() {
@@ -823,6 +908,26 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
     case 16: return launch_hop_ls<P, 16>(a, dagger, prologue, cfg, st, batch, nrhs);
     case 32: return launch_hop_ls<P, 32>(a, dagger, prologue, cfg, st, batch, nrhs);
     default: return launch_hop_ls<P, 0>(a, dagger, prologue, cfg, st, batch, nrhs);
+  }
+}
+
+template <typename P>
+int launch_hop_eo5(const HopArgs<P>& a0, const HopArgs<P>& a1, bool dagger, const LaunchCfg& cfg, hipStream_t st) {
+  const int LH = a0.Ls;
+  if (LH < 1 || 64 % LH != 0 || a1.Ls != LH || a1.nsites != a0.nsites) return -1;
+  if (cfg.ns != 1 || cfg.spb < 1 || cfg.spb * LH > 256) return -1;
+  for (const HopArgs<P>* a : {&a0, &a1}) {
+    if (a->E || a->epi_scan || a->out2.data || !a->loc.data || (a->sigma != 0 && a->sigma != 1)) return -1;
+    if (a->cg_r.data ? (!dagger || !a->cg_scalars) : !a->out.data) return -1;
+  }
+  if ((a0.cg_r.data == nullptr) != (a1.cg_r.data == nullptr)) return -1;
+  if (hop_lds_bytes<P>(cfg, LH, false) > 65536) return -1;
+  if (a0.nsites <= 0) return 0;
+  switch (LH) {
+    case 8: return launch_hop_eo5_ls<P, 8>(a0, a1, dagger, cfg, st);
+    case 16: return launch_hop_eo5_ls<P, 16>(a0, a1, dagger, cfg, st);
+    case 32: return launch_hop_eo5_ls<P, 32>(a0, a1, dagger, cfg, st);
+    default: return launch_hop_eo5_ls<P, 0>(a0, a1, dagger, cfg, st);
   }
 }
 
@@ -959,15 +1064,19 @@ inline long fifth_blocks(long nsites, int Ls, size_t elem) {
 
 #define DWF_HOP_LS_ONE(P, L)                                                                           \
   template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t, \
-                                        const HopArgs<P>*, int);
+                                        const HopArgs<P>*, int);                                       \
+  template int dwf::launch_hop_eo5_ls<P, L>(const HopArgs<P>&, const HopArgs<P>&, bool, const LaunchCfg&, hipStream_t);
 #define DWF_HOP_LS_EXTERN(P, L)                                                                               \
   extern template int dwf::launch_hop_ls<P, L>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t, \
-                                               const HopArgs<P>*, int);
+                                               const HopArgs<P>*, int);                                       \
+  extern template int dwf::launch_hop_eo5_ls<P, L>(const HopArgs<P>&, const HopArgs<P>&, bool, const LaunchCfg&, \
+                                                   hipStream_t);
 #define DWF_INSTANTIATE_HOP(P)                                                                                   \
   DWF_HOP_LS_EXTERN(P, 0) DWF_HOP_LS_EXTERN(P, 8) DWF_HOP_LS_EXTERN(P, 12) DWF_HOP_LS_EXTERN(P, 16)               \
   DWF_HOP_LS_EXTERN(P, 32)                                                                                      \
   template int dwf::launch_hop<P>(const HopArgs<P>&, bool, bool, const LaunchCfg&, hipStream_t,                \
                                   const HopArgs<P>*, int);                                                      \
   template int dwf::launch_hop_ilv<P>(const HopArgs<P>&, bool, int, const LaunchCfg&, hipStream_t);             \
+  template int dwf::launch_hop_eo5<P>(const HopArgs<P>&, const HopArgs<P>&, bool, const LaunchCfg&, hipStream_t); \
   template int dwf::launch_fifth<P>(CHalf<P>, Half<P>, const P::R*, const FifthScan<P::R>*, CHalf<P>, P::R,   \
                                     long, int, double*, hipStream_t);

@@ -59,6 +59,13 @@ struct HopArgs {
   const FifthScan<typename P::R>* es_tab = nullptr;
   const FifthScan<typename P::R>* es2_tab = nullptr;
   long part_stride = 0;
+  // 5D even-odd Shamir hop (launch_hop_eo5): loc = the input field's slices at the output sites
+  // (its half of the same 4D parity), sigma = the offset of the output slices (slot j holds
+  // s = 2 j + sigma; loc's slot j holds s = 2 j + 1 - sigma), r5 = the coefficient of the
+  // fifth-dimension hop (the 4D hop's is scale)
+  CHalf<P> loc = {nullptr, nullptr};
+  int sigma = 0;
+  typename P::R r5 = 0;
 };
 
 struct LaunchCfg {
@@ -83,6 +90,20 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
 // the hop on right-hand sides interleaved along s in segments of rs slices (see hop_impl.hpp)
 template <typename P>
 int launch_hop_ilv(const HopArgs<P>& a, bool dagger, int rs, const LaunchCfg& cfg, hipStream_t st);
+// The Shamir hop K = (5 - M5) - D(m) on 5D-checkerboarded fields: one launch over both 4D-parity
+// halves of the output field (a0: half 0, a1: half 1; workgroup pairs take the two halves of one
+// traversal tile).  Each half: out = ax x + scale H4(in) + r5 H5(loc), where in is the input
+// field's half of the other 4D parity (the hop's usual operand) and H5 the fifth-dimension hop
+// from loc.  a.Ls = Ls / 2 must divide 64; one slice per thread; no prologue or epilogue
+// matrices; the fused CG step only with the dagger.
+template <typename P>
+int launch_hop_eo5(const HopArgs<P>& a0, const HopArgs<P>& a1, bool dagger, const LaunchCfg& cfg, hipStream_t st);
+// The two 4D-parity halves h0, h1 of a field ([x_cb][12][Ls] each) <-> its two 5D-parity fields
+// ([4D parity q][x_cb][12][Ls/2] each: slice s of 4D parity q lies in field (s + q) mod 2, slot
+// s / 2); merge = 0 splits, 1 merges
+template <typename P>
+int launch_eo5_split(Half<P> h0, Half<P> h1, Half<P> f5_even, Half<P> f5_odd, long nsites, int Ls, int merge,
+                     hipStream_t st);
 
 // out = ax * x + E . in  (site-local fifth-dimension matrices), optional |out|^2 partials
 template <typename P>

@@ -288,6 +288,8 @@ struct Op {
   }
   // the scan epilogue can carry a second output (one s-slice per lane, Ls a wave segment)
   bool second_output_ok() const { return scan_ok && cfg.ns == 1 && (Ls == 8 || Ls == 16 || Ls == 32); }
+  // workgroups of one hop launch (the norm partials it writes)
+  long hop_blocks() const { return (g->nsites + cfg.spb - 1) / cfg.spb; }
   // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd);
   // ainvdag_out (optional, see second_output_ok): also A^-dag (M_prec psi)
   void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr,
@@ -332,6 +334,136 @@ struct Op {
       hop(0, in_o, out_e, true, false, -0.5, moebius ? em(E_FDAG) : nullptr, cv(out_e), 1.0);
       hop(1, in_e, out_o, true, false, -0.5, moebius ? em(E_FDAG) : nullptr, cv(out_o), 1.0);
     }
+  }
+};
+
+// ------------------------------------------------------------------ 5D even-odd (Shamir)
+// Shamir DWF checkerboarded in five dimensions, parity (x + y + z + t + s) mod 2:
+//   D = d0 - K,  d0 = 5 - M5,  K = 1/2 H4 + H5,  H5 psi_s = P- psi_{s+1} + P+ psi_{s-1}
+// (psi_{Ls} = -m psi_0, psi_{-1} = -m psi_{Ls-1}).  K connects opposite 5D parities only, so on
+// the even sites the Schur complement is  S = d0 - K_eo K_oe / d0.
+// A field of 5D parity p holds, for each 4D parity q, the slices s = 2 j + (p ^ q), j < Ls/2, of
+// every site x_cb of that parity: [q][x_cb][12][Ls/2].  Vector operations see it as one half
+// field of 2 nsites sites and Ls/2 slices (the geometry gv, which has no tables).
+template <typename P>
+struct Op5 {
+  using R = typename P::R;
+  using S = typename P::S;
+  dwf_ctx* ctx;
+  const Geometry* g4;
+  Geometry gv;
+  const Geometry* g = &gv;
+  int Ls;  // slices of one field per site: Ls / 2
+  double M5, m, d0;
+  const S* U[2];
+  LaunchCfg cfg;
+  // read by the CG driver: no Moebius input factor here
+  bool moebius = false, sdep = false;
+  double b = 1.0, c = 0.0;
+  const R* coef_b = nullptr;
+  const R* coef_c = nullptr;
+
+  Op5(const Op5&) = delete;
+  Op5& operator=(const Op5&) = delete;
+  Op5(dwf_ctx* ctx_, const Geometry* g4_, const dwf_params& p, const void* packed_links)
+      : ctx(ctx_), g4(g4_), Ls(p.Ls / 2), M5(p.M5), m(p.mass), d0(5.0 - p.M5) {
+    for (int k = 0; k < 4; ++k) gv.dims[k] = g4->dims[k];
+    gv.tbc = g4->tbc;
+    gv.V = g4->V;
+    gv.nsites = 2 * g4->nsites;
+    const S* base = reinterpret_cast<const S*>(packed_links);
+    U[0] = base;
+    U[1] = base + size_t(g4->nsites) * 72;
+    cfg = hop_config(ctx, P::ID, Ls);
+    cfg.ns = 1;
+    cfg.stage = 0;
+    cfg.off = 0;
+    if (cfg.spb < 1 || cfg.spb * Ls > 256) cfg.spb = 256 / Ls;
+  }
+  // the 4D-parity half q of a field
+  Half<P> half(Half<P> f, int q) const {
+    const size_t n = size_t(q) * g4->nsites * Ls;
+    return {f.data ? f.data + n * 12 : nullptr, f.norm ? f.norm + n : nullptr};
+  }
+  CHalf<P> half(CHalf<P> f, int q) const {
+    const size_t n = size_t(q) * g4->nsites * Ls;
+    return {f.data ? f.data + n * 12 : nullptr, f.norm ? f.norm + n : nullptr};
+  }
+  long hop_blocks() const { return 2 * ((g4->nsites + cfg.spb - 1) / cfg.spb); }
+  bool second_output_ok() const { return false; }
+  long n5() const { return gv.nsites * Ls; }
+
+  // out (5D parity p) = ax x + scale4 H4 in + r5 H5 in, in of parity 1 - p (dag: the adjoint
+  // hops); with cg_r: not stored, cg_r -= alpha (...) instead (dag only)
+  void K(int p, CHalf<P> in, Half<P> out, bool dag, double scale4, double r5, CHalf<P> x = {nullptr, nullptr},
+         double ax = 0.0, double* partials = nullptr, Half<P> cg_r = {nullptr, nullptr},
+         const double* scalars = nullptr) const {
+    HopArgs<P> a[2];
+    for (int q = 0; q < 2; ++q) {
+      HopArgs<P> h = HopArgs<P>();
+      h.in = half(in, 1 - q);
+      h.loc = half(in, q);
+      h.out = cg_r.data ? Half<P>{nullptr, nullptr} : half(out, q);
+      h.links = U[q];
+      h.nbr = g4->d_nbr[q];
+      h.order = g4->d_order[q];
+      h.nsites = g4->nsites;
+      h.Ls = Ls;
+      h.scale = R(scale4);
+      h.r5 = R(r5);
+      h.pb = R(1);
+      h.pc = R(0);
+      h.pm = R(m);
+      h.E = nullptr;
+      h.x = x.data ? half(x, q) : CHalf<P>{nullptr, nullptr};
+      h.ax = R(ax);
+      h.norm_partials = partials;
+      h.sigma = p ^ q;
+      if (cg_r.data) {
+        h.cg_r = half(cg_r, q);
+        h.cg_scalars = scalars;
+      }
+      a[q] = h;
+    }
+    long mark = -1;
+    if (ctx->timer.on) {
+      const int ls = (Ls == 8 || Ls == 16 || Ls == 32) ? Ls : 0;
+      mark = timer_begin(ctx, std::string("hop_eo5_kernel<") + prec_tag(P::ID) + ", " + std::to_string(ls) + ", " +
+                                  (dag ? "true" : "false") + ", " + (cfg.ll ? "true" : "false") + ", " +
+                                  (cg_r.data ? "true" : "false") + ">");
+    }
+    DWF_CHECK_LAUNCH(launch_hop_eo5<P>(a[0], a[1], dag, cfg, ctx->stream));
+    if (mark >= 0) {
+      const double fb = spinor_site_bytes<P>();
+      const double fields = cg_r.data ? 3 + (x.data ? 1 : 0) : 2 + (x.data ? 1 : 0);
+      timer_end(ctx, mark, double(n5()) * fb * fields + 2.0 * double(g4->nsites) * 72 * sizeof(S));
+    }
+  }
+  // S psi = d0 psi - K_eo K_oe psi / d0  (even -> even; tmp: an odd field)
+  void mprec(CHalf<P> in, Half<P> out, Half<P> tmp, double* partials = nullptr,
+             Half<P> unused = {nullptr, nullptr}) const {
+    (void)unused;
+    K(1, in, tmp, false, 0.5, 1.0);
+    K(0, cv(tmp), out, false, -0.5 / d0, -1.0 / d0, in, d0, partials);
+  }
+  void mprec_pre(CHalf<P> fin, CHalf<P> in, Half<P> out, Half<P> tmp, double* partials = nullptr,
+                 Half<P> unused = {nullptr, nullptr}) const {
+    (void)fin;
+    mprec(in, out, tmp, partials, unused);
+  }
+  // S^dag psi = d0 psi - K^dag_eo K^dag_oe psi / d0
+  void mprec_dag(CHalf<P> in, Half<P> out, Half<P> tmp_o, Half<P> tmp_e, double* partials = nullptr) const {
+    (void)tmp_e;
+    K(1, in, tmp_o, true, 0.5, 1.0);
+    K(0, cv(tmp_o), out, true, -0.5 / d0, -1.0 / d0, in, d0, partials);
+  }
+  // S^dag q with the CG step fused into its last hop (see Op::mprec_dag_cg)
+  void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, const double* scalars, double* partials,
+                    bool ready = false) const {
+    (void)tmp_e;
+    (void)ready;
+    K(1, in, tmp_o, true, 0.5, 1.0);
+    K(0, cv(tmp_o), Half<P>{nullptr, nullptr}, true, -0.5 / d0, -1.0 / d0, in, d0, partials, r, scalars);
   }
 };
 

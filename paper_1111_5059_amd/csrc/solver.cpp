@@ -57,8 +57,9 @@ static const void* links_in(dwf_ctx* ctx, const Geometry* g, const void* U64, in
 // x (FP64) holds the initial guess.  Iterations in storage precision Pi; for
 // Pi != FP64 the iterate increment accumulates in FP32 and is folded into the
 // FP64 x at every reliable update, where the residual is recomputed in FP64.
-template <typename Pi>
-static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf<P64> rhs, Half<P64> x,
+// OpT: Op (4D even-odd, M_prec) or Op5 (5D even-odd Shamir, its Schur complement S).
+template <typename Pi, template <typename> class OpT = Op>
+static int cg_normal(dwf_ctx* ctx, const OpT<P64>& op64, const OpT<Pi>& opi, CHalf<P64> rhs, Half<P64> x,
                      double tol_n, int maxit, double delta, const std::string& tag, SolveStats* st) {
   const Geometry* g = op64.g;
   const int Ls = op64.Ls;
@@ -146,7 +147,7 @@ static int cg_normal(dwf_ctx* ctx, const Op<P64>& op64, const Op<Pi>& opi, CHalf
   p_update(0.0, rr);
   double rr_max = rr, rr_true = rr;
   const bool OUT2 = opi.second_output_ok();
-  const long nb_hop = (g->nsites + opi.cfg.spb - 1) / opi.cfg.spb;
+  const long nb_hop = opi.hop_blocks();
   int it = 0;
   while (it < maxit) {
     const Half<Pi> p = pr[cur];
@@ -222,6 +223,147 @@ int normal_solve(dwf_ctx* ctx, const dwf_params& p, const void* U64, CHalf<P64> 
     case DWF_FP16: return cg_normal_dispatch<P16>(ctx, op64, p, U64, rhs, x, tol_n, maxit, delta, tag, st);
     default: return cg_normal_dispatch<PB16>(ctx, op64, p, U64, rhs, x, tol_n, maxit, delta, tag, st);
   }
+}
+
+// ------------------------------------------------------------------ 5D even-odd (Shamir)
+// the operator family the 5D checkerboard applies to: Shamir, Ls / 2 a divisor of 64 (a site's
+// slices of one 5D parity form one wave segment)
+static void eo5_check(const dwf_params& p) {
+  if (!(p.b == 1.0 && p.c == 0.0) || p.b_s || p.c_s)
+    throw Error{DWF_ERR_ARG, "the 5D even-odd operator is Shamir DWF only (b = 1, c = 0, constant)"};
+  if (p.Ls < 2 || p.Ls % 2 || 64 % (p.Ls / 2) != 0)
+    throw Error{DWF_ERR_ARG, "the 5D even-odd operator needs Ls in {2, 4, 8, 16, 32, 64, 128}"};
+}
+
+template <typename Pi>
+static int cg5_dispatch(dwf_ctx* ctx, const Op5<P64>& op64, const dwf_params& p, const void* U64, CHalf<P64> rhs,
+                        Half<P64> x, double tol_n, int maxit, double delta, const std::string& tag, SolveStats* st) {
+  const void* Ui = links_in(ctx, op64.g4, U64, Pi::ID, tag);
+  Op5<Pi> opi(ctx, op64.g4, p, Ui);
+  return cg_normal<Pi, Op5>(ctx, op64, opi, rhs, x, tol_n, maxit, delta, tag, st);
+}
+
+// D(m) x = b through the 5D even-odd Schur complement:
+//   b'_e = b_e + K_eo b_o / d0,  S^dag S x_e = S^dag b'_e  (CGNR),  x_o = (b_o + K_oe x_e) / d0,
+// tightening the normal-equation tolerance until ||b - D x|| / ||b|| <= tol (the residual through
+// the 4D even-odd operator's D).
+int solve_full_5d(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b, void* x, double tol, int maxit,
+                  double delta, const std::string& tag, dwf_solve_info* info) {
+  eo5_check(p);
+  const auto t0 = Clock::now();
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const int Ls = p.Ls;
+  const long n5 = g->nsites * Ls;
+  const size_t hb = half_size<P64>(g, Ls);
+  hipStream_t s = ctx->stream;
+  Op<P64> op(ctx, g, p, U64);
+  Op5<P64> op5(ctx, g, p, U64);
+  const Geometry* gv = op5.g;
+  const int LH = op5.Ls;
+  const double d0 = op5.d0;
+  const size_t fb = half_size<P64>(gv, LH);
+  auto field = [&](const char* name) { return hview<P64>(ws_get(ctx, tag + name, fb), gv, LH); };
+  Half<P64> be = field(".be"), bo = field(".bo"), xe = field(".xe"), xo = field(".xo"), bp = field(".bp"),
+            rhs = field(".rhs"), t1 = field(".t1"), t2 = field(".t2");
+  CHalf<P64> b4e = chalf_at<P64>(b, 0, g, Ls), b4o = chalf_at<P64>(b, hb, g, Ls);
+  Half<P64> x4e = half_at<P64>(x, 0, g, Ls), x4o = half_at<P64>(x, hb, g, Ls);
+  void* rfull = ws_get(ctx, tag + ".rfull", 2 * hb);
+  Half<P64> re = half_at<P64>(rfull, 0, g, Ls), ro = half_at<P64>(rfull, hb, g, Ls);
+
+  const double b2 = norm2_sync<P64>(ctx, b4e, g, Ls) + norm2_sync<P64>(ctx, b4o, g, Ls);
+  if (!std::isfinite(b2)) throw Error{DWF_ERR_NAN, "non-finite source"};
+  SolveStats st;
+  int status = 0;
+  double rel = 0.0;
+  if (b2 == 0.0) {
+    DWF_CHECK_LAUNCH(launch_zero(x, 2 * hb, s));
+  } else {
+    DWF_CHECK_LAUNCH(launch_eo5_split<P64>(Half<P64>{const_cast<double2*>(b4e.data), nullptr},
+                                           Half<P64>{const_cast<double2*>(b4o.data), nullptr}, be, bo, g->nsites, Ls,
+                                           0, s));
+    // the initial guess: x split the same way (a zero x gives zero fields)
+    DWF_CHECK_LAUNCH(launch_eo5_split<P64>(x4e, x4o, xe, xo, g->nsites, Ls, 0, s));
+    op5.K(0, cv(bo), bp, false, 0.5 / d0, 1.0 / d0, cv(be), 1.0);  // b'_e
+    op5.mprec_dag(cv(bp), rhs, t1, t2);                            // S^dag b'_e
+    double tol_n = tol;
+    status = 1;
+    for (int attempt = 0; attempt < 12; ++attempt) {
+      const int left = maxit - st.iters;
+      if (left <= 0) break;
+      switch (p.prec_inner) {
+        case DWF_FP64: cg5_dispatch<P64>(ctx, op5, p, U64, cv(rhs), xe, tol_n, left, delta, tag + ".cg", &st); break;
+        case DWF_FP32: cg5_dispatch<P32>(ctx, op5, p, U64, cv(rhs), xe, tol_n, left, delta, tag + ".cg", &st); break;
+        case DWF_FP16: cg5_dispatch<P16>(ctx, op5, p, U64, cv(rhs), xe, tol_n, left, delta, tag + ".cg", &st); break;
+        default: cg5_dispatch<PB16>(ctx, op5, p, U64, cv(rhs), xe, tol_n, left, delta, tag + ".cg", &st); break;
+      }
+      op5.K(1, cv(xe), xo, false, 0.5 / d0, 1.0 / d0, cv(bo), 1.0 / d0);  // x_o
+      DWF_CHECK_LAUNCH(launch_eo5_split<P64>(x4e, x4o, xe, xo, g->nsites, Ls, 1, s));
+      // true residual of the full system (4D even-odd D)
+      op.full(cv(x4e), cv(x4o), re, ro, false);
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, b4e, -1.0, re, n5, Ls, s));
+      DWF_CHECK_LAUNCH(launch_axpby<P64>(1.0, b4o, -1.0, ro, n5, Ls, s));
+      const double r2 = norm2_sync<P64>(ctx, cv(re), g, Ls) + norm2_sync<P64>(ctx, cv(ro), g, Ls);
+      rel = std::sqrt(r2 / b2);
+      if (!std::isfinite(rel)) throw Error{DWF_ERR_NAN, "non-finite true residual"};
+      if (rel <= tol) {
+        status = 0;
+        break;
+      }
+      tol_n *= std::max(0.02, std::min(0.5, 0.5 * tol / rel));
+      st.restarts++;
+    }
+  }
+  DWF_CHECK_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = st.iters;
+    info->reliable_updates = st.reliable_updates;
+    info->restarts = st.restarts;
+    info->true_rel_resid = rel;
+    info->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    info->wilson_apps = (long long)st.iters * Ls;
+  }
+  return status;
+}
+
+// one application of K (op 0: both 5D parities) or S (op 1: the even 5D parity; the odd part of
+// out is zero) in precision P on packed fields of that precision
+template <typename P>
+static void dslash_5d_t(dwf_ctx* ctx, const dwf_params& p, const void* U, const void* in, void* out, int op,
+                        bool dag) {
+  const Geometry* g = geometry(ctx, p.dims, p.tbc);
+  const int Ls = p.Ls;
+  const size_t hb = half_size<P>(g, Ls);
+  hipStream_t s = ctx->stream;
+  Op5<P> op5(ctx, g, p, U);
+  const Geometry* gv = op5.g;
+  const int LH = op5.Ls;
+  const size_t fb = half_size<P>(gv, LH);
+  auto field = [&](const char* name) { return hview<P>(ws_get(ctx, std::string("d5") + name, fb), gv, LH); };
+  Half<P> ie = field(".ie"), io = field(".io"), oe = field(".oe"), oo = field(".oo"), t = field(".t");
+  Half<P> i4e = hview<P>(const_cast<void*>(in), g, Ls), i4o = hview<P>(reinterpret_cast<char*>(const_cast<void*>(in)) + hb, g, Ls);
+  Half<P> o4e = hview<P>(out, g, Ls), o4o = hview<P>(reinterpret_cast<char*>(out) + hb, g, Ls);
+  DWF_CHECK_LAUNCH(launch_eo5_split<P>(i4e, i4o, ie, io, g->nsites, Ls, 0, s));
+  if (op == 0) {
+    op5.K(0, cv(io), oe, dag, 0.5, 1.0);
+    op5.K(1, cv(ie), oo, dag, 0.5, 1.0);
+  } else {
+    if (dag) op5.mprec_dag(cv(ie), oe, t, oo);
+    else op5.mprec(cv(ie), oe, t);
+    DWF_CHECK_LAUNCH(launch_zero(oo.data, fb, s));  // (the FP16 norms follow the data in the buffer)
+  }
+  DWF_CHECK_LAUNCH(launch_eo5_split<P>(o4e, o4o, oe, oo, g->nsites, Ls, 1, s));
+}
+
+int dslash_5d(dwf_ctx* ctx, const dwf_params& p, const void* U, const void* in, void* out, int op, int dagger) {
+  eo5_check(p);
+  if (op != 0 && op != 1) throw Error{DWF_ERR_ARG, "op must be 0 (K) or 1 (S)"};
+  switch (p.prec) {
+    case DWF_FP64: dslash_5d_t<P64>(ctx, p, U, in, out, op, dagger != 0); break;
+    case DWF_FP32: dslash_5d_t<P32>(ctx, p, U, in, out, op, dagger != 0); break;
+    case DWF_FP16: dslash_5d_t<P16>(ctx, p, U, in, out, op, dagger != 0); break;
+    default: dslash_5d_t<PB16>(ctx, p, U, in, out, op, dagger != 0); break;
+  }
+  return 0;
 }
 
 // ------------------------------------------------------------------ full-system solve

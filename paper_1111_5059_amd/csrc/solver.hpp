@@ -16,6 +16,9 @@ int normal_solve(dwf_ctx* ctx, const dwf_params& p, const void* U64, CHalf<P64> 
                  int maxit, double delta, const std::string& tag, SolveStats* st);
 int solve_full(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b, void* x, double tol, int maxit,
                double delta, const std::string& tag, dwf_solve_info* info);
+int solve_full_5d(dwf_ctx* ctx, const dwf_params& p, const void* U64, const void* b, void* x, double tol, int maxit,
+                  double delta, const std::string& tag, dwf_solve_info* info);
+int dslash_5d(dwf_ctx* ctx, const dwf_params& p, const void* U, const void* in, void* out, int op, int dagger);
 int solve_batched(dwf_ctx* ctx, int nrhs, const dwf_params* P, const void* const* U64, const void* const* b,
                   void* const* x, dwf_solve_info* info);
 int madwf(dwf_ctx* ctx, const dwf_params& pt, const dwf_params& pi, const void* U64, const void* b, void* x,

@@ -105,6 +105,25 @@ def test_cg_ne_zero_source(env):
     assert info["converged"] and np.all(lat.unpack_np(xg) == 0)
 
 
+def test_workspace_release_keeps_results(env):
+    """dwf_ctx_release frees the workspace; the next solve allocates it again and gives the same
+    (bit-identical) solution in the same number of iterations."""
+    import torch
+    dwf, ctx = env
+    dims, Ls = (4, 4, 2, 4), 8
+    lat = dwf.Lattice(ctx, dims, Ls, mass=0.05)
+    Ug = lat.pack_gauge(synth.random_links(dims, 0.4, 9))
+    bg = lat.pack(synth.gaussian_spinor(dims, Ls, 10))
+    runs = []
+    for _ in range(2):
+        x = lat.zeros(dwf.KIND_FULL)
+        info = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.FP32), Ug, bg, x, tol=1e-10)
+        runs.append((info["iters"], x))
+        ctx.release()
+    assert runs[0][0] == runs[1][0]
+    assert torch.equal(runs[0][1], runs[1][1])
+
+
 def test_cg_ne_nan_source_is_an_error(env):
     dwf, ctx = env
     dims, Ls = (2, 2, 2, 2), 4

@@ -268,6 +268,55 @@ def test_dense_solve_and_schur(ora, dense_setup):
     assert np.max(np.abs(Morc - Mdense)) < 1e-12
 
 
+def parity5_flat(dims, Ls):
+    shape = (Ls, dims[3], dims[2], dims[1], dims[0], 4, 3)
+    p5 = (np.arange(Ls)[:, None, None, None, None] + synth.parity_array(dims)[None]) & 1
+    return np.broadcast_to(p5[..., None, None], shape).ravel()
+
+
+@pytest.fixture(scope="module")
+def dense_shamir5(ora, dense_setup):
+    """Dense Shamir D(m) on 2^4 x Ls=4 (m = 0.1, antiperiodic in T) and the 5D parities"""
+    dims, Ls, U = dense_setup
+    p = ora.params(dims, Ls, M5=1.8, mass=0.1, tbc=1)
+    D = dense_matrix(lambda v: ora.dwf(p, U, v), (Ls, 2, 2, 2, 2, 4, 3))
+    return D, parity5_flat(dims, Ls)
+
+
+def test_shamir_operator_on_the_5d_checkerboard(ora, dense_setup, dense_shamir5):
+    """Shamir D(m) - (5 - M5) has no matrix element between sites of equal 5D parity
+    (x + y + z + t + s) mod 2 (the 4D hop changes x, the fifth-dimension hop changes s); a Moebius
+    operator's c D_W (P- psi_{s+1} + P+ psi_{s-1}) term does couple them (x and s change together):
+    a point source at (x, s) reaches (x + mu, s + 1)."""
+    D, par = dense_shamir5
+    K = (5 - 1.8) * np.eye(D.shape[0]) - D
+    assert np.max(np.abs(K[np.equal.outer(par, par)])) < 1e-15
+    assert np.max(np.abs(K)) > 0.4
+    dims, Ls, U = dense_setup
+    pm = ora.params(dims, Ls, M5=1.8, mass=0.1, b=1.5, c=0.5)
+    v = np.zeros((Ls, 2, 2, 2, 2, 4, 3), complex)
+    v[1, 0, 0, 0, 0, 0, 0] = 1.0  # s = 1, site 0, spin 0 (P+): P+ psi_{s-1} feeds s = 2
+    Dv = ora.dwf(pm, U, v)
+    assert np.max(np.abs(Dv[2, 0, 0, 0, 1])) > 0.1  # (x + 1, s + 1): equal 5D parity
+
+
+def test_5d_schur_route_solves_d(ora, dense_shamir5):
+    """The route of the 5D even-odd solver: b'_e = b_e + K_eo b_o / d0, S x_e = b'_e with
+    S = d0 - K_eo K_oe / d0, x_o = (b_o + K_oe x_e) / d0, gives the dense solution of D x = b."""
+    D, par = dense_shamir5
+    d0 = 5 - 1.8
+    K = d0 * np.eye(D.shape[0]) - D
+    e, o = np.where(par == 0)[0], np.where(par == 1)[0]
+    b = synth.gaussian_spinor((2, 2, 2, 2), 4, 53).ravel()
+    S = d0 * np.eye(len(e)) - K[np.ix_(e, o)] @ K[np.ix_(o, e)] / d0
+    xe = np.linalg.solve(S, b[e] + K[np.ix_(e, o)] @ b[o] / d0)
+    xo = (b[o] + K[np.ix_(o, e)] @ xe) / d0
+    x = np.zeros_like(b)
+    x[e], x[o] = xe, xo
+    x_dense = np.linalg.solve(D, b)
+    assert np.linalg.norm(x - x_dense) <= 1e-12 * np.linalg.norm(x_dense)
+
+
 def dense_dw(ora, dims, U, M5):
     p4 = ora.params(dims, 1, M5=M5)
     return dense_matrix(lambda v: ora.dw4(p4, U, v), (2, 2, 2, 2, 4, 3))
