@@ -139,6 +139,9 @@ def apply_operators(dwf, ctx, lat, inner, U64, bg, prec, iters=4):
             rng.manual_seed(11)
             b.view(torch.float64).normal_(generator=rng)
         dwf.cg_ne(ctx, lt.params(prec_inner=P), U64, b, x, tol=1e-14, maxit=iters)
+        if lt is lat:  # and the 5D even-odd solver's hops
+            x.zero_()
+            dwf.cg_ne_5d(ctx, lt.params(prec_inner=P), U64, b, x, tol=1e-14, maxit=iters)
         torch.cuda.synchronize()
         del x, b
 
@@ -230,6 +233,11 @@ def batched_cfg5(dwf, prec="fp32", tol=1e-10, eps=0.5):
     log(f"cfg5: batched shape {best} ({best_ms:.1f} ms per iteration of 8), searched {len(table)} shapes "
         f"in {time.perf_counter() - t:.1f} s")
     pars = [lat.params(mass=m, prec_inner=P) for m, _ in rhs]
+    # workspace allocated before timing, as for the solves one at a time (after the search freed it,
+    # allocating it again takes seconds)
+    dwf.cg_ne_batched(ctx, pars, U64, [bs[k] for _, k in rhs], xs, tol=tol, maxit=2)
+    for x in xs:
+        x.zero_()
     torch.cuda.synchronize()
     t = time.perf_counter()
     bat = dwf.cg_ne_batched(ctx, pars, U64, [bs[k] for _, k in rhs], xs, tol=tol)

@@ -187,26 +187,28 @@ __device__ __forceinline__ void store_spinor(Half<P> f, long x, int s, int Ls, c
 //   mu=y: h0 = psi0 - sg psi3,   h1 = psi1 + sg psi2;   r2 = sg h1,   r3 = -sg h0
 //   mu=z: h0 = psi0 - sg i psi2, h1 = psi1 + sg i psi3; r2 = sg i h0, r3 = -sg i h1
 //   mu=t: h0 = psi0 + sg psi2,   h1 = psi1 + sg psi3;   r2 = sg h0,   r3 = sg h1
+// the two rows for one colour, from the four spin components p0..p3 of that colour
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void project_colour(cx<R> p0, cx<R> p1, cx<R> p2, cx<R> p3, cx<R>& h0, cx<R>& h1) {
+  const R sg = R(SG);
+  if constexpr (MU == 0) {
+    h0 = p0 - sg * ci(p3);
+    h1 = p1 - sg * ci(p2);
+  } else if constexpr (MU == 1) {
+    h0 = p0 - sg * p3;
+    h1 = p1 + sg * p2;
+  } else if constexpr (MU == 2) {
+    h0 = p0 - sg * ci(p2);
+    h1 = p1 + sg * ci(p3);
+  } else {
+    h0 = p0 + sg * p2;
+    h1 = p1 + sg * p3;
+  }
+}
 template <int MU, int SG, typename R>
 __device__ __forceinline__ void project(const cx<R> psi[12], cx<R> h[6]) {
-  const R sg = R(SG);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cx<R> p0 = psi[0 * 3 + c], p1 = psi[1 * 3 + c], p2 = psi[2 * 3 + c], p3 = psi[3 * 3 + c];
-    if constexpr (MU == 0) {
-      h[c] = p0 - sg * ci(p3);
-      h[3 + c] = p1 - sg * ci(p2);
-    } else if constexpr (MU == 1) {
-      h[c] = p0 - sg * p3;
-      h[3 + c] = p1 + sg * p2;
-    } else if constexpr (MU == 2) {
-      h[c] = p0 - sg * ci(p2);
-      h[3 + c] = p1 + sg * ci(p3);
-    } else {
-      h[c] = p0 + sg * p2;
-      h[3 + c] = p1 + sg * p3;
-    }
-  }
+  for (int c = 0; c < 3; ++c) project_colour<MU, SG, R>(psi[c], psi[3 + c], psi[6 + c], psi[9 + c], h[c], h[3 + c]);
 }
 
 // acc += (1 + sg g_mu)-reconstruction of the projected, link-multiplied half spinor u

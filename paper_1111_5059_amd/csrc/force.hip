@@ -18,25 +18,30 @@ using C = cx<double>;
 
 __device__ __forceinline__ C cconj(C a) { return {a.re, -a.im}; }
 
+// The spin trace of the projected outer product: with P = 1 + sg g_mu (hermitian, and P^2 = 2P),
+//   sum_spin [P w] z^+ = h0(w) h0(z)^+ + h1(w) h1(z)^+,
+// h0, h1 the two independent rows of the projection (device.hpp); so each slice contributes
+// two 3x3 colour outer products of projected half spinors.
 template <int MU, int SG>
-__device__ __forceinline__ void spin_project_full(const C w[12], C pw[12]) {
-  C h[6];
-  project<MU, SG>(w, h);
+__device__ __forceinline__ void load_project(CHalf<P64> f, long x, int s, int Ls, C h[6]) {
+  const double2* p = f.data + size_t(x) * 12 * Ls + s;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) pw[k] = {0.0, 0.0};
-  reconstruct_acc<MU, SG>(h, pw);
+  for (int c = 0; c < 3; ++c)
+    project_colour<MU, SG, double>(P64::ld(p[c * Ls]), P64::ld(p[(3 + c) * Ls]), P64::ld(p[(6 + c) * Ls]),
+                                   P64::ld(p[(9 + c) * Ls]), h[c], h[3 + c]);
 }
 
 template <int MU, int SG>
-__device__ __forceinline__ void outer_acc(const C w[12], const C z[12], C Q[9]) {
-  C pw[12];
-  spin_project_full<MU, SG>(w, pw);
+__device__ __forceinline__ void proj_outer_acc(CHalf<P64> W, long xw, CHalf<P64> Z, long xz, int s, int Ls, C Q[9]) {
+  C hw[6], hz[6];
+  load_project<MU, SG>(W, xw, s, Ls, hw);
+  load_project<MU, SG>(Z, xz, s, Ls, hz);
 #pragma unroll
-  for (int be = 0; be < 4; ++be)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Q[r * 3 + c] = cfma(pw[be * 3 + r], cconj(z[be * 3 + c]), Q[r * 3 + c]);
+      for (int j = 0; j < 3; ++j) Q[i * 3 + j] = cfma(hw[r * 3 + i], cconj(hz[r * 3 + j]), Q[i * 3 + j]);
 }
 
 struct ForceArgs {
@@ -52,93 +57,91 @@ struct ForceArgs {
   double2* F;
 };
 
-// Lane layout: the SEG lanes of one aligned wave segment share one link and take the slices
-// s = lane, lane + SEG, ... of the fifth dimension, so that their loads of the s-fastest
-// [x_cb][12][Ls] fields are contiguous.  The partial sums of Q1 and Q2 are then added across the
-// segment by butterfly shuffles (fixed order), and the segment's first lane writes the link.
-template <int SEG>
-__device__ __forceinline__ double seg_sum(double v) {
+// Lane layout: the SEG lanes (SEG >= 16) of one aligned wave segment share one link and take the
+// slices s = lane, lane + SEG, ... of the fifth dimension, so that their loads of the s-fastest
+// [x_cb][12][Ls] fields are contiguous.  The lanes' partial sums of Q1 (then Q2) go to LDS, and lane
+// e < 9 of the segment adds element e (row e / 3, column e % 3) over the segment's lanes in lane
+// order; it then computes element e of the link's result, taking the other elements it needs
+// from the lanes that hold them.  One 3x3 accumulator is live at a time.
+__device__ __forceinline__ C shfl_c(C v, int src) { return {__shfl(v.re, src, 64), __shfl(v.im, src, 64)}; }
+
+// the segment sum of one slice loop's outer products, element e (< 9) of it in lane e
+template <int MU, int SG, int SEG>
+__device__ __forceinline__ C link_term(CHalf<P64> W, long xw, CHalf<P64> Z, long xz, int Ls, int lane, bool active,
+                                       C* part) {
+  C Q[9];
 #pragma unroll
-  for (int off = 1; off < SEG; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  for (int k = 0; k < 9; ++k) Q[k] = {0.0, 0.0};
+  if (active) {
+#pragma unroll 1
+    for (int s = lane; s < Ls; s += SEG) proj_outer_acc<MU, SG>(W, xw, Z, xz, s, Ls, Q);
+  }
+  C* mine = part + threadIdx.x * 9;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) mine[k] = Q[k];
+  __syncthreads();
+  C sum = {0.0, 0.0};
+  if (lane < 9) {
+    const C* seg = part + (threadIdx.x - lane) * 9 + lane;
+    for (int i = 0; i < SEG; ++i) sum = sum + seg[i * 9];
+  }
+  __syncthreads();  // (the buffer is reused by the next term)
+  return sum;
 }
 
 template <int MU, int SEG>
-__device__ void force_link(const ForceArgs& a, int p, long x, int lane, bool active) {
-  C Q1[9], Q2[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Q1[k] = Q2[k] = {0.0, 0.0};
-  const long xf = active ? a.nbr[p][x * 8 + MU] : 0;
-  if (active) {
-    for (int s = lane; s < a.Ls; s += SEG) {
-      C w[12], z[12];
-      load_spinor<P64>(a.W[1 - p], xf, s, a.Ls, w);
-      load_spinor<P64>(a.Z[p], x, s, a.Ls, z);
-      outer_acc<MU, -1>(w, z, Q1);
-      load_spinor<P64>(a.W[p], x, s, a.Ls, w);
-      load_spinor<P64>(a.Z[1 - p], xf, s, a.Ls, z);
-      outer_acc<MU, +1>(w, z, Q2);
-    }
-  }
-  // (every lane of the segment takes part in the shuffles: active is uniform over a segment)
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    Q1[k] = {seg_sum<SEG>(Q1[k].re), seg_sum<SEG>(Q1[k].im)};
-    Q2[k] = {seg_sum<SEG>(Q2[k].re), seg_sum<SEG>(Q2[k].im)};
-  }
-  if (!active || lane != 0) return;
-  const int code = a.linksrc[p][x * 8 + MU];
+__device__ void force_link(const ForceArgs& a, int p, long x, int lane, bool active, C* part) {
+  static_assert(SEG >= 16 && SEG <= 64, "a segment holds the nine elements of a link");
+  // (the parity's operands selected, not indexed: a runtime index into the argument arrays would
+  // copy them to private memory)
+  const int* nbr = p ? a.nbr[1] : a.nbr[0];
+  const int* lsrc = p ? a.linksrc[1] : a.linksrc[0];
+  const CHalf<P64> Wp = p ? a.W[1] : a.W[0], Wq = p ? a.W[0] : a.W[1];
+  const CHalf<P64> Zp = p ? a.Z[1] : a.Z[0], Zq = p ? a.Z[0] : a.Z[1];
+  const long xf = active ? nbr[x * 8 + MU] : 0;
+  const int base = int(threadIdx.x & 63) - lane;  // first lane of the segment in the wave
+  const int e = lane < 9 ? lane : 8;              // (lanes >= 9 repeat element 8 and store nothing)
+  const int r = e / 3, c = e - 3 * r;
+  const C q1 = link_term<MU, -1, SEG>(Wq, xf, Zp, x, a.Ls, lane, active, part);
+  const C q2 = link_term<MU, +1, SEG>(Wp, x, Zq, xf, a.Ls, lane, active, part);
+  int code = 0;
+  if (active) code = lsrc[x * 8 + MU];
   const long l = code >> 1;
   const double ph = (code & 1) ? -1.0 : 1.0;
-  C U[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) U[k] = {ph * a.U[l * 9 + k].x, ph * a.U[l * 9 + k].y};
-  C out[9];
+  C out;
   if (a.kind == 0) {
-    // M = Q2 U^+ - U Q1 ; F = -1/2 [ (M - M^+)/2 - tr(M - M^+)/6 ]
-    C M[9];
+    // M = Q2 U^+ - U Q1 ; F = -1/2 [ (M - M^+)/2 - tr(M - M^+)/6 ]:  M[r][c] and M[c][r] here
+    C mrc = {0.0, 0.0}, mcr = {0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        C m = {0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          m = cfma(Q2[r * 3 + k], cconj(U[c * 3 + k]), m);
-          m = m - cmul(U[r * 3 + k], Q1[k * 3 + c]);
-        }
-        M[r * 3 + c] = m;
+    for (int k = 0; k < 3; ++k) {
+      const C q2rk = shfl_c(q2, base + r * 3 + k), q2ck = shfl_c(q2, base + c * 3 + k);
+      const C q1kc = shfl_c(q1, base + k * 3 + c), q1kr = shfl_c(q1, base + k * 3 + r);
+      C urk = {0.0, 0.0}, uck = {0.0, 0.0};
+      if (active) {
+        urk = {ph * a.U[l * 9 + r * 3 + k].x, ph * a.U[l * 9 + r * 3 + k].y};
+        uck = {ph * a.U[l * 9 + c * 3 + k].x, ph * a.U[l * 9 + c * 3 + k].y};
       }
-    const double trim = (M[0].im + M[4].im + M[8].im);  // tr(M - M^+) = 2 i Im tr M
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const C a1 = M[r * 3 + c], a2 = cconj(M[c * 3 + r]);
-        C ta = {0.5 * (a1.re - a2.re), 0.5 * (a1.im - a2.im)};
-        if (r == c) ta.im -= trim / 3.0;
-        out[r * 3 + c] = {-0.5 * ta.re, -0.5 * ta.im};
-      }
+      mrc = cfma(q2rk, cconj(uck), mrc) - cmul(urk, q1kc);
+      mcr = cfma(q2ck, cconj(urk), mcr) - cmul(uck, q1kr);
+    }
+    // tr(M - M^+) = 2 i Im tr M: the diagonal elements are held by lanes 0, 4, 8
+    const double trim = __shfl(mrc.im, base + 0, 64) + __shfl(mrc.im, base + 4, 64) + __shfl(mrc.im, base + 8, 64);
+    C ta = {0.5 * (mrc.re - mcr.re), 0.5 * (mrc.im + mcr.im)};
+    if (r == c) ta.im -= trim / 3.0;
+    out = {-0.5 * ta.re, -0.5 * ta.im};
   } else {
     // G = -ph (Q1^+ + Q2)
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const C g = cconj(Q1[c * 3 + r]) + Q2[r * 3 + c];
-        out[r * 3 + c] = {-ph * g.re, -ph * g.im};
-      }
+    const C q1t = shfl_c(q1, base + c * 3 + r);
+    out = {-ph * (q1t.re + q2.re), -ph * (-q1t.im + q2.im)};
   }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    double2 v = make_double2(a.coef * out[k].re, a.coef * out[k].im);
-    if (a.accumulate) {
-      const double2 o = a.F[l * 9 + k];
-      v.x += o.x;
-      v.y += o.y;
-    }
-    a.F[l * 9 + k] = v;
+  if (!active || lane >= 9) return;
+  double2 v = make_double2(a.coef * out.re, a.coef * out.im);
+  if (a.accumulate) {
+    const double2 o = a.F[l * 9 + e];
+    v.x += o.x;
+    v.y += o.y;
   }
+  a.F[l * 9 + e] = v;
 }
 
 // SEG lanes per link (SEG a power of two, at least Ls when Ls <= 64).  One wave takes 64 / SEG
@@ -155,11 +158,12 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs a) {
   const bool active = j < 2 * a.nsites;
   const int p = j >= a.nsites ? 1 : 0;
   const long x = active ? j - p * a.nsites : 0;
+  __shared__ C part[256 * 9];  // the lanes' partial sums of one term
   switch (mu) {
-    case 0: force_link<0, SEG>(a, p, x, lane, active); break;
-    case 1: force_link<1, SEG>(a, p, x, lane, active); break;
-    case 2: force_link<2, SEG>(a, p, x, lane, active); break;
-    default: force_link<3, SEG>(a, p, x, lane, active); break;
+    case 0: force_link<0, SEG>(a, p, x, lane, active, part); break;
+    case 1: force_link<1, SEG>(a, p, x, lane, active, part); break;
+    case 2: force_link<2, SEG>(a, p, x, lane, active, part); break;
+    default: force_link<3, SEG>(a, p, x, lane, active, part); break;
   }
 }
 
@@ -180,17 +184,14 @@ int launch_force(const GeomTables& g, int Ls, CHalf<P64> W_e, CHalf<P64> W_o, CH
   a.coef = coef;
   a.accumulate = accumulate;
   a.F = F;
-  // lanes per link: the smallest power of two covering Ls, at most 64; 4 waves per 64 / seg sites
-  int seg = 1;
+  // lanes per link: the smallest power of two covering Ls, at least 16 (the nine elements of the
+  // result are spread over the segment) and at most 64; 4 waves per 64 / seg sites
+  int seg = 16;
   while (seg < Ls && seg < 64) seg <<= 1;
   const long spw = 64 / seg;
   const long waves = 4 * ((2 * g.nsites + spw - 1) / spw);
   const unsigned blocks = (unsigned)((waves * 64 + 255) / 256);
   switch (seg) {
-    case 1: hipLaunchKernelGGL(force_kernel<1>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(force_kernel<2>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(force_kernel<4>, dim3(blocks), dim3(256), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(force_kernel<8>, dim3(blocks), dim3(256), 0, st, a); break;
     case 16: hipLaunchKernelGGL(force_kernel<16>, dim3(blocks), dim3(256), 0, st, a); break;
     case 32: hipLaunchKernelGGL(force_kernel<32>, dim3(blocks), dim3(256), 0, st, a); break;
     default: hipLaunchKernelGGL(force_kernel<64>, dim3(blocks), dim3(256), 0, st, a); break;

@@ -54,7 +54,7 @@ def counter_per_dispatch(path, kernel_substring, counter):
     return vals, grids
 
 
-FAMILIES = ("hop_kernel<", "fifth_kernel<")
+FAMILIES = ("hop_kernel<", "hop_eo5_kernel<", "hop_ilv_kernel<", "hop_batch_kernel<", "fifth_kernel<", "force_kernel<")
 
 
 def short_name(full):
