@@ -758,10 +758,10 @@ int launch_hop_ilv(const HopArgs<P>& a, bool dagger, int rs, const LaunchCfg& cf
 // 4D parities of one traversal tile, dispatched together (and with the XCD-aware order on one
 // XCD), so that each input half read as neighbours by one is read as loc by the other while it
 // is in that XCD's L2.
-// (no occupancy floor: with the fifth-dimension hop's operand the FP16 body spills at 4 waves
-// per SIMD)
+// (occupancy floor of 4 waves per SIMD only for FP32 with links in LDS: the other bodies spill
+// there with the fifth-dimension hop's operand)
 template <typename P, int LS, bool DAG, bool LL, bool CG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, ((std::is_same<P, P32>::value && LL) ? 4 : 1))
     hop_eo5_kernel(HopArgs<P> a0, HopArgs<P> a1, int spb, int xcd) {
   const long b = xcd ? xcd_block(blockIdx.x, gridDim.x) : (long)blockIdx.x;
   // (one body per half: the arguments stay in the kernel-argument segment, no private copy)
