@@ -129,6 +129,28 @@ def test_batch_respects_maxit(env, prec):
             x.zero_()
 
 
+def test_batch_beyond_one_launch(env, ora):
+    """Nine Shamir right-hand sides at Ls = 32: the interleaved hop takes at most 256 / Ls = 8 per
+    launch, so they run as a chunk of 8 and a chunk of 1; a tenth at Ls = 12 (no interleaved form) in
+    the same call runs on a separate field.  Every solve reaches 1e-10 through the oracle's D."""
+    dwf, ctx = env
+    dims = (4, 2, 2, 4)
+    U = synth.random_links(dims, 0.4, 1801)
+    lats = {Ls: dwf.Lattice(ctx, dims, Ls, M5=1.8) for Ls in (32, 12)}
+    Ug = lats[32].pack_gauge(U)
+    cases = [(32, 0.01 * (k + 1)) for k in range(9)] + [(12, 0.05)]
+    srcs = [synth.gaussian_spinor(dims, Ls, 1810 + k) for k, (Ls, _) in enumerate(cases)]
+    pars = [lats[Ls].params(mass=m, prec_inner=dwf.FP32) for Ls, m in cases]
+    bs = [lats[Ls].pack(b) for (Ls, _), b in zip(cases, srcs)]
+    xs = [lats[Ls].zeros(dwf.KIND_FULL) for Ls, _ in cases]
+    infos = dwf.cg_ne_batched(ctx, pars, Ug, bs, xs, tol=1e-10)
+    for k, ((Ls, m), info) in enumerate(zip(cases, infos)):
+        assert info["converged"], (k, info)
+        po = ora.params(dims, Ls, M5=1.8, mass=m)
+        r = srcs[k] - ora.dwf(po, U, lats[Ls].unpack_np(xs[k]))
+        assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(srcs[k]), (k, Ls, m)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
 def test_every_batched_shape_solves(env, ora, prec):
     """Every shape the batched tuner may install (right-hand sides interleaved along s, or on

@@ -165,13 +165,16 @@ def test_madwf_matches_oracle(env, ora, prec_mob):
         assert abs(np.log10(g_r) - np.log10(o_r)) < 0.5
 
 
+@pytest.mark.parametrize("Ls", [6, 20, 32, 40])
 @pytest.mark.parametrize("bc,tbc", [((1.0, 0.0), 0), ((1.5, 0.5), 1)])
-def test_force_kernel_parity(env, ora, bc, tbc):
+def test_force_kernel_parity(env, ora, bc, tbc, Ls):
     """Force at given X (the oracle's, solved to 1e-14): GPU outer-product kernel vs the
-    oracle's per-generator definition, 1e-10; also the ambient gradient kind."""
+    oracle's per-generator definition, 1e-10; also the ambient gradient kind.  Ls 6 and 20 leave
+    lanes of the link's 16- and 32-lane segments idle, 32 fills a segment, 40 takes two slices per
+    lane of a 64-lane segment."""
     import torch
     dwf, ctx = env
-    dims, Ls = (4, 4, 2, 4), 6
+    dims = (4, 4, 2, 4)
     U = synth.random_links(dims, 0.5, 1301)
     phi = synth.gaussian_spinor_parity(dims, Ls, 1302, 1)
     po = ora.params(dims, Ls, mass=0.05, b=bc[0], c=bc[1], tbc=tbc)
