@@ -129,6 +129,25 @@ def test_batch_respects_maxit(env, prec):
             x.zero_()
 
 
+def test_bf16_interleaved_ladder(env, ora):
+    """BF16 storage in the interleaved batch: each right-hand side restarts its Krylov space at its
+    reliable updates (as the single solve does) and still reaches 1e-10 through the oracle's D."""
+    dwf, ctx = env
+    dims, Ls = (4, 4, 2, 4), 16
+    masses = [0.02, 0.1, 0.4]
+    U = synth.random_links(dims, 0.4, 1820)
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8)
+    srcs = [synth.gaussian_spinor(dims, Ls, 1830 + k) for k in range(len(masses))]
+    xs = [lat.zeros(dwf.KIND_FULL) for _ in masses]
+    infos = dwf.cg_ne_batched(ctx, [lat.params(mass=m, prec_inner=dwf.BF16) for m in masses], lat.pack_gauge(U),
+                              [lat.pack(b) for b in srcs], xs, tol=1e-10)
+    for k, (m, info) in enumerate(zip(masses, infos)):
+        assert info["converged"] and info["reliable_updates"] >= 1, (k, info)
+        po = ora.params(dims, Ls, M5=1.8, mass=m)
+        r = srcs[k] - ora.dwf(po, U, lat.unpack_np(xs[k]))
+        assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(srcs[k]), (k, m)
+
+
 def test_batch_beyond_one_launch(env, ora):
     """Nine Shamir right-hand sides at Ls = 32: the interleaved hop takes at most 256 / Ls = 8 per
     launch, so they run as a chunk of 8 and a chunk of 1; a tenth at Ls = 12 (no interleaved form) in

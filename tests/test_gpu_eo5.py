@@ -5,7 +5,8 @@ With d0 = 5 - M5 the Shamir operator is D(m) = d0 - K, K connecting opposite 5D 
 K psi = d0 psi - D psi, and the even-site Schur complement S psi_e = d0 psi_e - P_e K P_o K psi_e / d0.
 Every application is compared in the four storage precisions at their tolerances; the solver
 reaches the full-system true residual through the oracle's D.  Extents give a ragged last
-workgroup; Ls 8 runs the runtime-extent kernel, Ls 16 and 32 the compile-time ones.
+workgroup; Ls 2, 4 and 8 run the runtime-extent kernel (one, two and four lanes per site), Ls 16, 32
+and 64 the compile-time ones.
 """
 import numpy as np
 import pytest
@@ -15,7 +16,8 @@ from gpu_helpers import PREC_TOL, gpu_ctx, rel_err
 
 pytestmark = pytest.mark.gpu
 
-CASES = [((6, 4, 6, 10), 8), ((4, 4, 2, 6), 16), ((2, 4, 2, 6), 32)]
+CASES = [((6, 4, 6, 10), 8), ((4, 4, 2, 6), 16), ((2, 4, 2, 6), 32), ((2, 2, 2, 4), 64), ((4, 2, 2, 2), 4),
+         ((2, 2, 4, 2), 2)]
 
 
 @pytest.fixture(scope="module")
