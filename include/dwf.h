@@ -204,7 +204,8 @@ int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void*
  * x_o = (b_o + K_oe x_e) / d0, to the full-system true residual info->tol (computed with the
  * 4D even-odd D(m) of cg_ne).  Arguments, precisions, reliable updates, info and errors as
  * cg_ne; x holds the initial guess.  Workspace (held by ctx): the fields of cg_ne's iteration,
- * each one 5D-parity field (the size of one packed half), plus eight FP64 5D-parity fields.
+ * each one 5D-parity field (the size of one packed half), plus eight FP64 5D-parity fields and
+ * one FP64 full field (the true residual).
  *
  * dwf_dslash_5d: one application of op on packed full fields of precision p->prec (U packed
  * in p->prec): DWF_OP5_HOP out = K in (dagger: K^+ in); DWF_OP5_SCHUR: the even-5D-parity part
