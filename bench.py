@@ -539,6 +539,8 @@ def main():
     ap.add_argument("--batched-cfg5", action="store_true",
                     help="only the 8-right-hand-side batched solve on 32^3x64, Ls=16 (about 180 GB of HBM; "
                          "prints its own JSON line)")
+    ap.add_argument("--force-cfg4", action="store_true",
+                    help="only the 16^3x32, Ls=16 force configuration (prints its own JSON line)")
     ap.add_argument("--no-cfg5", action="store_true",
                     help="skip the 8-right-hand-side batched solve that otherwise ends the run")
     ap.add_argument("--madwf-scan", action="store_true",
@@ -560,6 +562,10 @@ def main():
     if args.madwf_scan:
         torch.cuda.set_device(0)
         print(json.dumps(madwf_scan_run(dwf)))
+        return
+    if args.force_cfg4:
+        torch.cuda.set_device(0)
+        print(json.dumps(cfg4_measure(dwf)))
         return
 
     dims, L, mass, eps, Lp, bm, cm, desc = WORKLOADS[args.workload]
