@@ -1354,7 +1354,7 @@ static void force_terms(dwf_ctx* ctx, const Op<P64>& op, const void* Unat, CHalf
 }
 
 // S and the force at the links Unat.  X solves M^dag M X = phi to the normal-equation tolerance
-// tol_n, judged by the FP64 true residual ||phi - M^dag M X|| / ||phi|| recomputed after the
+// tol_n, checked by the FP64 true residual ||phi - M^dag M X|| / ||phi|| recomputed after the
 // solve (the stop test of an FP64 recurrence uses its iterated residual); while it is above tol_n
 // the solve continues from X with a tightened stop, within maxit iterations in all.  *converged
 // turns false if it does not get there; *true_rel receives the largest true residual seen.
