@@ -436,8 +436,9 @@ def cfg4_measure(dwf, tau=0.1):
     """Fermion force (Sec. 2) of S = phi^dag (M_prec^dag M_prec)^-1 phi on 16^3 x 32, Ls = 16,
     m = 0.01 (eps = 0.5 links, Gaussian phi on odd sites), FP64 solve to 1e-10: the call's time, the
     force kernel's time and bandwidth (library timer, algorithmic bytes: the four FP64 half fields
-    it contracts, the links and the force once), and the force-gradient step at tau = 0.1 with its
-    second solve started from the first (iterations at U and at U')."""
+    it contracts, the links and the force once), the same force from FP32 solver iterations with FP64
+    reliable updates, and the force-gradient step at tau = 0.1 with its second solve started from the
+    first (iterations at U and at U')."""
     import torch
     import synth
     dims, Ls = (16, 16, 16, 32), 16
@@ -463,6 +464,18 @@ def cfg4_measure(dwf, tau=0.1):
     rep = dwf.dwf_timing_report(ctx)
     dwf.dwf_timing_enable(ctx, False)
     fk = rep.get("force_kernel")
+    # the same force with FP32 solver iterations (FP64 reliable updates, FP64 solution): time and
+    # its distance from the FP64-iteration force
+    F32 = torch.zeros_like(Ud)
+    p32 = lat.params(prec_inner=dwf.FP32)
+    dwf.fermion_force(ctx, p32, Ud, phi, F32, tol=1e-10, maxit=5)  # allocations
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    info32 = dwf.fermion_force(ctx, p32, Ud, phi, F32, tol=1e-10)
+    torch.cuda.synchronize()
+    secs32 = time.perf_counter() - t
+    d32 = float((F32 - F).abs().max() / F.abs().max())
+    del F32
     F1 = torch.zeros_like(Ud)
     dwf.fermion_force(ctx, lat.params(), Ud, phi_hb, F1, tol=1e-10)
     t = time.perf_counter()
@@ -478,6 +491,9 @@ def cfg4_measure(dwf, tau=0.1):
     out = {"workload": "fermion force, Shamir DWF 16^3x32 Ls=16 M5=1.8 mf=0.01, random SU(3) links eps=0.5, Gaussian "
                        "phi on odd sites, FP64 solve to a normal-equation residual of 1e-10",
            "seconds": secs, "iters": info["iters"], "converged": info["converged"],
+           "fp32_iterations": {"seconds": secs32, "iters": info32["iters"],
+                               "reliable_updates": info32["reliable_updates"], "converged": info32["converged"],
+                               "max_rel_diff_from_fp64_force": d32},
            "force_kernel": None,
            "fg_step": {"tau": tau, "phi": "M^dag eta, eta Gaussian on odd sites", "seconds": fg_secs,
                        "iters_first": fg["iters_first"], "iters_forecast": fg["iters"] - fg["iters_first"],
@@ -487,6 +503,8 @@ def cfg4_measure(dwf, tau=0.1):
         out["force_kernel"] = {"avg_ms": ms, "bytes_per_launch": fk["bytes"] / fk["launches"],
                                "GBps": fk["bytes"] / fk["launches"] / (ms * 1e-3) / 1e9}
         log(f"cfg4 force kernel: {ms:.3f} ms, {out['force_kernel']['GBps']:.0f} GB/s")
+    log(f"cfg4 force with FP32 iterations: {secs32:.2f} s ({info32['iters']} iterations), max relative "
+        f"difference from the FP64-iteration force {d32:.1e}")
     log(f"cfg4 force: {secs:.2f} s ({info['iters']} iterations); FG step: {fg['iters_first']} + "
         f"{fg['iters'] - fg['iters_first']} iterations (from zero at U': {zero['iters']})")
     return out

@@ -97,6 +97,24 @@ def test_force_matches_oracle_at_sampled_links(env, ora, force_state):
     assert err < 1e-10
 
 
+def test_force_with_fp32_iterations(env, force_state):
+    """The force from FP32 solver iterations (FP64 reliable updates, FP64 solution) to the same
+    normal-equation tolerance: converged, and within 1e-8 of the FP64-iteration force (both solutions
+    meet 1e-12, so they differ by less than the operator's condition number times that)."""
+    import torch
+    dwf, ctx = env
+    st = force_state
+    lat = st["lat"]
+    F = torch.zeros_like(st["Ud"])
+    info = dwf.fermion_force(ctx, lat.params(prec_inner=dwf.FP32), st["Ud"], st["phig"], F, tol=1e-12)
+    print("fp32-iteration force solve", info)
+    assert info["converged"] and info["reliable_updates"] >= 1
+    F = F.cpu().numpy()
+    err = rel_err(F, st["F"])
+    print("fp32 vs fp64 iterations, force rel diff", err)
+    assert err < 1e-8
+
+
 def action_variational(dwf, ctx, lat, Ud, phig, x):
     """S at the links Ud from a solve warm-started at x (updated in place): the estimate
     2 Re <phi, X> - |M X|^2, whose error is quadratic in the solve's error."""
