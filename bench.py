@@ -322,14 +322,16 @@ def sdep_measure(dwf, ctx, lat, U64, prec="fp16", reps=10):
     return out
 
 
-def cpu_baseline(workload, U, fp64_iters, seconds_budget=25.0):
+def cpu_baseline(workload, U, fp64_iters, seconds_budget=25.0, cfg2_iters=None):
     """FP64 oracle on the host cores, timed on a bounded sample of the workload: its
     M_prec^dag M_prec at the workload's full Ls on a slab of the lattice (the same spatial
     extent, T = 4; the oracle's cost per site does not depend on the volume, and its dense
     (4 Ls)^2 fifth-dimension blocks make it grow faster than linearly in Ls, so Ls is not
     reduced), scaled by the volume ratio and by the iteration count of the plain FP64 GPU solve.
-    Beside it, one oracle CGNR solve of the 4^4, Ls = 8 system to a true residual of 1e-10,
-    timed whole."""
+    Beside it: one Wilson hop on the same slab; one oracle CGNR solve of the 4^4, Ls = 8 system to a
+    true residual of 1e-10, timed whole; on the 16^3 x 32, Ls = 16 lattice one hop, one
+    M_prec^dag M_prec (scaled by the GPU's FP64 iteration count there when given) and one force
+    evaluation at a given X."""
     import oracle
     import synth
     dims, L, mass = workload[0], workload[1], workload[2]
@@ -349,6 +351,9 @@ def cpu_baseline(workload, U, fp64_iters, seconds_budget=25.0):
     dt = (time.perf_counter() - t0) / reps
     vol_ratio = dims[3] / slab[3]
     per_iter_full = dt * vol_ratio
+    t = time.perf_counter()
+    oracle.hop5(p, Us, psi, out_parity=0)
+    hop_slab = time.perf_counter() - t
     # cfg1, timed directly
     d1 = (4, 4, 4, 4)
     U1 = synth.random_links(d1, 0.3, synth.link_seed(1))
@@ -356,12 +361,33 @@ def cpu_baseline(workload, U, fp64_iters, seconds_budget=25.0):
     t1 = time.perf_counter()
     _, info1 = oracle.solve(oracle.params(d1, 8, M5=1.8, mass=0.01), U1, b1, tol=1e-10)
     cfg1_s = time.perf_counter() - t1
+    # the 16^3 x 32, Ls = 16 lattice of the solver and force configurations
+    d2, L2 = (16, 16, 16, 32), 16
+    U2 = synth.random_links(d2, 0.5, synth.link_seed(2))
+    p2 = oracle.params(d2, L2, M5=1.8, mass=0.01)
+    psi2 = synth.gaussian_spinor_parity(d2, L2, synth.source_seed(2, 9), 1)
+    t = time.perf_counter()
+    oracle.hop5(p2, U2, psi2, out_parity=0)
+    hop2 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.mprec(p2, U2, oracle.mprec(p2, U2, psi2), dagger=True)
+    mdm2 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.force(p2, U2, psi2)
+    force2 = time.perf_counter() - t
+    cfg2 = {"workload": "Shamir DWF 16^3x32 Ls=16 M5=1.8 mf=0.01, eps=0.5 links", "hop_s": hop2,
+            "mdagm_s": mdm2, "force_at_X_s": force2}
+    if cfg2_iters:
+        cfg2["cg_extrapolated_s"] = mdm2 * cfg2_iters
+        cfg2["cg_iterations_scaled"] = cfg2_iters
     return {"value": per_iter_full * fp64_iters, "unit": "s", "cores": nthreads, "kind": "oracle",
             "sample": f"{reps} x M_prec^dag M_prec of the FP64 oracle at Ls={L} on a {slab} slab of the "
                       f"{dims} lattice ({dt:.2f} s each), scaled by the volume ratio {vol_ratio:g} and by the "
                       f"{fp64_iters} CG iterations of the plain FP64 GPU solve (extrapolated time-to-solution "
                       f"of the oracle's CGNR)",
             "seconds_per_iteration": per_iter_full,
+            "hop_seconds": hop_slab * vol_ratio,
+            "cfg2_lattice": cfg2,
             "cfg1_direct": {"workload": "Shamir DWF 4^4 Ls=8 M5=1.8 mf=0.01, eps=0.3 links, CGNR to a true "
                                         "residual 1e-10, timed whole", "seconds": cfg1_s,
                             "iters": info1["iters"], "true_rel_resid": info1["true_rel_resid"]}}
@@ -702,7 +728,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and fp64 is not None:
         log("CPU oracle baseline ...")
-        cpu = cpu_baseline(WORKLOADS[args.workload], U, fp64["iters"])
+        cpu = cpu_baseline(WORKLOADS[args.workload], U, fp64["iters"],
+                           cfg2_iters=cfg2["fp64_cg"]["iters"] if cfg2 else None)
         log(f"oracle: {cpu['seconds_per_iteration']:.2f} s per CG iteration on {cpu['cores']} threads; cfg1 solve "
             f"{cpu['cfg1_direct']['seconds']:.2f} s")
 
