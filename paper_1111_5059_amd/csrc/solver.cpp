@@ -500,20 +500,21 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
   double* dcoef = reinterpret_cast<double*>(ws_get(ctx, "ilv.coef", size_t(2) * K0 * sizeof(double)));
   const size_t nscan = size_t(3) * K0;
   FifthScan<R>* dscan = reinterpret_cast<FifthScan<R>*>(ws_get(ctx, "ilv.scan", nscan * sizeof(FifthScan<R>)));
-  // pinned host mirrors: scalars, p-update coefficients, fifth-dimension tables
-  double* hsc = nullptr;
-  double* hcoef = nullptr;
-  FifthScan<R>* hscan = nullptr;
-  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsc), size_t(K0) * S_COUNT * sizeof(double)));
-  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hcoef), size_t(2) * K0 * sizeof(double)));
-  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hscan), nscan * sizeof(FifthScan<R>)));
+  // pinned host mirrors: scalars, p-update coefficients, fifth-dimension tables (freed on every
+  // exit, also when a later allocation throws)
   struct HostFree {
-    void* p[3];
+    void* p[3] = {nullptr, nullptr, nullptr};
     ~HostFree() {
       for (void* q : p)
         if (q) (void)hipHostFree(q);
     }
-  } host_free{{hsc, hcoef, hscan}};
+  } host_free;
+  DWF_CHECK_HIP(hipHostMalloc(&host_free.p[0], size_t(K0) * S_COUNT * sizeof(double)));
+  DWF_CHECK_HIP(hipHostMalloc(&host_free.p[1], size_t(2) * K0 * sizeof(double)));
+  DWF_CHECK_HIP(hipHostMalloc(&host_free.p[2], nscan * sizeof(FifthScan<R>)));
+  double* hsc = static_cast<double*>(host_free.p[0]);
+  double* hcoef = static_cast<double*>(host_free.p[1]);
+  FifthScan<R>* hscan = static_cast<FifthScan<R>*>(host_free.p[2]);
   // interleaved inner vectors (sized for all K0 right-hand sides)
   const size_t hbi = half_bytes<Pi>(ns, LT0);
   void* rb = ws_get(ctx, "ilv.r", hbi);
@@ -820,20 +821,20 @@ static void cg_batched_fields(dwf_ctx* ctx, std::vector<BatchSys>& S, int maxit,
   }
   double* part = reinterpret_cast<double*>(ws_get(ctx, "batch.partials", size_t(K) * pstride * sizeof(double)));
   double* sc = reinterpret_cast<double*>(ws_get(ctx, "batch.scalars", size_t(K) * S_COUNT * sizeof(double)));
-  double* hsc = nullptr;
-  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&hsc), size_t(K) * S_COUNT * sizeof(double)));
-  // pinned host and device tables of the four stages' launch arguments
-  HopArgs<Pi>* htab = nullptr;
-  DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&htab), size_t(4) * K * sizeof(HopArgs<Pi>)));
-  HopArgs<Pi>* dtab = reinterpret_cast<HopArgs<Pi>*>(ws_get(ctx, "batch.table", size_t(4) * K * sizeof(HopArgs<Pi>)));
+  // pinned host scalars and the host table of the four stages' launch arguments (freed on every
+  // exit, also when a later allocation throws)
   struct HostFree {
-    double* a;
-    HopArgs<Pi>* b;
+    void* p[2] = {nullptr, nullptr};
     ~HostFree() {
-      if (a) (void)hipHostFree(a);
-      if (b) (void)hipHostFree(b);
+      for (void* q : p)
+        if (q) (void)hipHostFree(q);
     }
-  } host_free{hsc, htab};
+  } host_free;
+  DWF_CHECK_HIP(hipHostMalloc(&host_free.p[0], size_t(K) * S_COUNT * sizeof(double)));
+  DWF_CHECK_HIP(hipHostMalloc(&host_free.p[1], size_t(4) * K * sizeof(HopArgs<Pi>)));
+  double* hsc = static_cast<double*>(host_free.p[0]);
+  HopArgs<Pi>* htab = static_cast<HopArgs<Pi>*>(host_free.p[1]);
+  HopArgs<Pi>* dtab = reinterpret_cast<HopArgs<Pi>*>(ws_get(ctx, "batch.table", size_t(4) * K * sizeof(HopArgs<Pi>)));
   // FP64 temporaries shared by the reliable updates (largest system)
   void* rhi_raw = ws_get(ctx, "batch.rhi", hb64max);
   void* t64a_raw = ws_get(ctx, "batch.t64a", hb64max);
