@@ -184,12 +184,12 @@ const char* dwf_last_error(void) { return dwf::last_error(); }
 int dwf_ctx_create(dwf_ctx** out, void* stream) {
   if (!out) return fail(DWF_ERR_ARG, "ctx out-pointer is NULL");
   return guarded([&]() {
-    auto* c = new dwf_ctx();
+    std::unique_ptr<dwf_ctx> c(new dwf_ctx());  // (freed if a step below fails)
     c->stream = reinterpret_cast<hipStream_t>(stream);
     DWF_CHECK_HIP(hipGetDevice(&c->device));
     scratch_init();  // device address of the no-allocation entry point's array on this device
     DWF_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_scalars), S_COUNT * sizeof(double)));
-    *out = c;
+    *out = c.release();
     return DWF_OK;
   });
 }
