@@ -445,6 +445,44 @@ __device__ __forceinline__ void eo5_fifth_hop(const HopArgs<P>& a, typename P::R
   }
 }
 
+// FP16: the same with the operand kept packed until it is used; the neighbouring lane's six
+// components and its norm travel as 32-bit words (one shuffle per complex number)
+template <bool DAG>
+__device__ __forceinline__ void eo5_fifth_hop_f16(const HopArgs<P16>& a, float r5, long x, int j, int LH, bool active,
+                                                  cx<float> acc[12]) {
+  int w[12];
+  float n = 0.0f;
+  if (active) {
+    const int* p = reinterpret_cast<const int*>(a.loc.data) + size_t(x) * 12 * LH + j;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = p[k * LH];
+    n = a.loc.norm[size_t(x) * LH + j];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = 0;
+  }
+  const int sigma = a.sigma;
+  const bool nbr_minus = (sigma != 0) != DAG;
+  const bool wrap = sigma ? (j == LH - 1) : (j == 0);
+  const int jn = sigma ? (wrap ? 0 : j + 1) : (wrap ? LH - 1 : j - 1);
+  const int src = int(threadIdx.x & 63) - j + jn;
+  const float cn = (wrap ? -a.pm * r5 : r5) * __shfl(n, src, 64);  // the neighbour's norm
+  const float co = r5 * n;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const f16x2 hn = __builtin_bit_cast(f16x2, __shfl(nbr_minus ? w[6 + k] : w[k], src, 64));
+    const f16x2 ho = __builtin_bit_cast(f16x2, nbr_minus ? w[k] : w[6 + k]);
+    const cx<float> vn = {cn * float(hn.x), cn * float(hn.y)}, vo = {co * float(ho.x), co * float(ho.y)};
+    if (nbr_minus) {
+      acc[6 + k] = acc[6 + k] + vn;
+      acc[k] = acc[k] + vo;
+    } else {
+      acc[k] = acc[k] + vn;
+      acc[6 + k] = acc[6 + k] + vo;
+    }
+  }
+}
+
 template <typename P, int LS, int NS, bool DAG, bool PRO, int EPI, bool LL, bool CG, bool ST, int RS = 0,
           bool EO5 = false>
 __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pidx, int spb) {
@@ -562,7 +600,8 @@ __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pid
   if constexpr (EO5) {
     // (placed after the gathers: before them it raises the register count further)
     static_assert(NS == 1 && !PRO && EPI == 0 && RS == 0 && !ST, "5D even-odd hop: one slice per lane, no matrices");
-    eo5_fifth_hop<P, DAG>(a, a.r5, x, s0, Ls, active, acc[0]);
+    if constexpr (std::is_same<P, P16>::value) eo5_fifth_hop_f16<DAG>(a, a.r5, x, s0, Ls, active, acc[0]);
+    else eo5_fifth_hop<P, DAG>(a, a.r5, x, s0, Ls, active, acc[0]);
   }
   // the lane's right-hand side and slice within it (interleaved fields)
   const int rhs = RS > 0 ? s0 / (RS > 0 ? RS : 1) : 0;
