@@ -504,6 +504,13 @@ __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pid
       if constexpr (EPI == 3) es_lds[1][i] = a.es2_tab[i];
     }
     __syncthreads();
+  } else if constexpr (RS > 0 && CG) {
+    // (the fused CG step's operator on the axpy operand, per right-hand side: see x_es2)
+    if (a.x_es2) {
+      const int K = Ls / RS;
+      for (int i = threadIdx.x; i < K; i += blockDim.x) es_lds[0][i] = a.es2_tab[i];
+      __syncthreads();
+    }
   }
   const int lsite = threadIdx.x / tps;
   const int s0 = threadIdx.x - lsite * tps;
@@ -653,6 +660,11 @@ __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pid
       }
     }
   }
+  // the axpy operand given through a site-local operator (x_es2): es2 applied along the site's
+  // segment right after the read (every lane of a site is active or inactive together, so the
+  // segment's shuffles read active lanes only)
+  constexpr bool XS = CG && NS == 1 && RS == 0 && !ST && !std::is_same<P, P64>::value && (LS == 8 || LS == 16 || LS == 32);
+  constexpr bool XSI = CG && RS > 0 && EPI < 2 && !std::is_same<P, P64>::value;  // per right-hand side
   double nrm = 0.0;
   if (active) {
     const R alpha = CG ? R(a.cg_scalars[rhs * S_COUNT + S_ALPHA]) : R(0);
@@ -662,6 +674,11 @@ __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pid
       if (a.x.data) {
         cx<R> xv[12];
         load_spinor<P>(a.x, x, s, Ls, xv);
+        if constexpr (XS) {
+          if (a.x_es2) fifth_scan_apply<(LS > 0 ? LS : 1)>(xv, s, a.es2);
+        } else if constexpr (XSI) {
+          if (a.x_es2) fifth_scan_apply<(RS > 0 ? RS : 1)>(xv, sr, es_lds[0][rhs]);
+        }
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[j][k] = acc[j][k] + a.ax * xv[k];
       }
@@ -683,7 +700,8 @@ __device__ __forceinline__ void hop_body(const HopArgs<P>& a, long bid, long pid
           for (int k = 0; k < 12; ++k)
             nrm += double(acc[j][k].re) * double(acc[j][k].re) + double(acc[j][k].im) * double(acc[j][k].im);
         }
-        store_spinor<P>(a.out, x, s, Ls, acc[j]);
+        // (no out with a second output: only the norm and out2 are wanted)
+        if (a.out.data) store_spinor<P>(a.out, x, s, Ls, acc[j]);
       }
     }
   }
@@ -783,6 +801,9 @@ int launch_hop_ilv(const HopArgs<P>& a, bool dagger, int rs, const LaunchCfg& cf
   if (a.Ls < rs || a.Ls % rs != 0 || cfg.ns != 1 || cfg.spb < 1 || cfg.spb * a.Ls > 256) return -1;
   if (a.E || (a.epi_scan && !a.es_tab) || (a.out2.data && (!a.epi_scan || !a.es2_tab || dagger))) return -1;
   if (a.cg_r.data && (!dagger || !a.cg_scalars)) return -1;
+  if (!a.cg_r.data && !a.out.data && !a.out2.data) return -1;
+  // the operator on the fused CG step's axpy operand: per right-hand side from es2_tab
+  if (a.x_es2 && (!a.cg_r.data || !a.x.data || !a.es2_tab || a.epi_scan || std::is_same<P, P64>::value)) return -1;
   if (a.norm_partials && a.part_stride < (a.nsites + cfg.spb - 1) / cfg.spb) return -1;
   if (hop_lds_bytes<P>(cfg, a.Ls, false) > 65536) return -1;
   if (a.nsites <= 0) return 0;
@@ -934,6 +955,11 @@ int launch_hop(const HopArgs<P>& a, bool dagger, bool prologue, const LaunchCfg&
   if (a.Ls % cfg.ns != 0 || cfg.spb < 1) return -1;
   if (dagger && prologue) return -1;
   if (a.cg_r.data && (!dagger || !a.cg_scalars)) return -1;
+  // the operator on the axpy operand and a missing out need the scan shapes (one slice per
+  // lane, the site's Ls lanes a wave segment)
+  const bool seg_shape = cfg.ns == 1 && (a.Ls == 8 || a.Ls == 16 || a.Ls == 32);
+  if (a.x_es2 && (!a.cg_r.data || !a.x.data || !x_es2_shape<P>(cfg, a.Ls) || batch)) return -1;
+  if (!a.cg_r.data && !a.out.data && !(a.out2.data && a.E && a.epi_scan && seg_shape)) return -1;
   const int threads = cfg.spb * (a.Ls / cfg.ns);
   if (threads > 256) return -1;
   if (hop_lds_bytes<P>(cfg, a.Ls, a.E != nullptr) > 65536) return -1;

@@ -43,6 +43,11 @@ struct HopArgs {
   int epi_scan = 0;            // es is valid (used when the site's lanes form a wave segment)
   CHalf<P> x;                  // axpy operand (data == nullptr: none)
   typename P::R ax;
+  // x_es2 != 0 (fused CG step, scan epilogue shapes only): the axpy operand is es2 . x, the
+  // site-local operator applied to x in registers (the CG hop then reads A^-dag q, which it
+  // turns back into q = A^dag (A^-dag q), and q itself need not be stored); interleaved right-
+  // hand sides take the operator of each from es2_tab
+  int x_es2 = 0;
   double* norm_partials;       // per-block sum |out|^2 (|cg_r|^2 with the fused CG step) or nullptr
   // second output (scan epilogue only): out2 = es2 . out, a site-local operator applied to
   // the final result (out2.data == nullptr: none)
@@ -79,6 +84,14 @@ struct LaunchCfg {
 // the launch shape the LDS-staged hop runs with
 inline bool stage_shape(const LaunchCfg& cfg, int Ls) {
   return cfg.stage && cfg.ns == 1 && cfg.spb * Ls == 256 && (Ls == 8 || Ls == 16 || Ls == 32);
+}
+
+// the launches that apply a site-local operator to the fused CG step's axpy operand
+// (HopArgs::x_es2): one slice per lane, the site's Ls lanes a wave segment, not the LDS-staged
+// shape, and not FP64 storage (where the extra live operand costs a wave per SIMD)
+template <typename P>
+inline bool x_es2_shape(const LaunchCfg& cfg, int Ls) {
+  return !std::is_same<P, P64>::value && cfg.ns == 1 && (Ls == 8 || Ls == 16 || Ls == 32) && !stage_shape(cfg, Ls);
 }
 
 // batch: optional device table of nrhs fields' arguments for one launch over all of them (a is

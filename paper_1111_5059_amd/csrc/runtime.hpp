@@ -206,6 +206,7 @@ struct Op {
   struct CgStep {
     Half<P> r = {nullptr, nullptr};
     const double* scalars = nullptr;
+    int x_slot = -1;  // >= 0: the axpy operand is es[x_slot] . x (applied in the launch)
   };
 
   // the launch arguments of one hop (see hop)
@@ -240,6 +241,10 @@ struct Op {
     }
     a.x = x;
     a.ax = R(ax);
+    if (cg.x_slot >= 0) {
+      a.es2 = es[cg.x_slot];
+      a.x_es2 = 1;
+    }
     a.norm_partials = partials;
     return a;
   }
@@ -248,7 +253,8 @@ struct Op {
   double hop_bytes(const HopArgs<P>& a) const {
     const double fb = spinor_site_bytes<P>();
     const bool xin = a.x.data != nullptr;
-    const double bytes = a.cg_r.data ? fb * (3 + (xin ? 1 : 0)) : fb * (2 + (xin ? 1 : 0) + (a.out2.data ? 1 : 0));
+    const double bytes = a.cg_r.data ? fb * (3 + (xin ? 1 : 0))
+                                     : fb * (1 + (a.out.data ? 1 : 0) + (xin ? 1 : 0) + (a.out2.data ? 1 : 0));
     return double(n5()) * bytes + double(g->nsites) * 72 * sizeof(S);
   }
   // out2 (optional): slot2 applied to the final result, a second output of the same launch
@@ -288,10 +294,13 @@ struct Op {
   }
   // the scan epilogue can carry a second output (one s-slice per lane, Ls a wave segment)
   bool second_output_ok() const { return scan_ok && cfg.ns == 1 && (Ls == 8 || Ls == 16 || Ls == 32); }
+  // ... and the last hop of M^dag q can rebuild q from that second output (q need not be stored)
+  bool rebuild_q_ok() const { return second_output_ok() && x_es2_shape<P>(cfg, Ls); }
   // workgroups of one hop launch (the norm partials it writes)
   long hop_blocks() const { return (g->nsites + cfg.spb - 1) / cfg.spb; }
   // M_prec psi = psi - 1/4 A^-1 H_oe F A^-1 H_eo F psi      (odd -> odd);
-  // ainvdag_out (optional, see second_output_ok): also A^-dag (M_prec psi)
+  // ainvdag_out (optional, see second_output_ok): also A^-dag (M_prec psi); with it, out may be
+  // empty (the norm partials and A^-dag (M_prec psi) only)
   void mprec(CHalf<P> in, Half<P> out, Half<P> tmp_e, double* partials = nullptr,
              Half<P> ainvdag_out = {nullptr, nullptr}) const {
     hop(0, in, tmp_e, false, true, 1.0, em(E_AINV));
@@ -312,16 +321,19 @@ struct Op {
   }
   // M_prec^dag q with the CG step fused into its last hop: r -= alpha M_prec^dag q and the
   // per-workgroup partials of |r|^2 (alpha read from scalars on the device)
-  // (ainvdag_ready: tmp_o already holds A^-dag in, the second output of mprec)
+  // (ainvdag_ready: tmp_o already holds A^-dag q, the second output of mprec; q_rebuilt (needs
+  // rebuild_q_ok): in is not read, the last hop forms q = A^dag (A^-dag q) at its own sites)
   void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, const double* scalars, double* partials,
-                    bool ainvdag_ready = false) const {
+                    bool ainvdag_ready = false, bool q_rebuilt = false) const {
     if (!ainvdag_ready) fifth(in, tmp_o, E_AINVDAG);
     hop(0, cv(tmp_o), tmp_e, true, false, 1.0, em(E_AINVDAG_FDAG));
     CgStep cg;
     cg.r = r;
     cg.scalars = scalars;
-    hop(1, cv(tmp_e), Half<P>{nullptr, nullptr}, true, false, -0.25, moebius ? em(E_FDAG) : nullptr, in, 1.0, partials,
-        cg);
+    const bool reb = ainvdag_ready && q_rebuilt;
+    if (reb) cg.x_slot = E_ADAG;
+    hop(1, cv(tmp_e), Half<P>{nullptr, nullptr}, true, false, -0.25, moebius ? em(E_FDAG) : nullptr,
+        reb ? cv(tmp_o) : in, 1.0, partials, cg);
   }
   // full D (or D^dag):  (D psi)_p = A psi_p - 1/2 H F psi_{1-p};  (D^dag psi)_p = A^dag psi_p - 1/2 F^dag H^dag psi_{1-p}
   void full(CHalf<P> in_e, CHalf<P> in_o, Half<P> out_e, Half<P> out_o, bool dag) const {
@@ -391,6 +403,7 @@ struct Op5 {
   }
   long hop_blocks() const { return 2 * ((g4->nsites + cfg.spb - 1) / cfg.spb); }
   bool second_output_ok() const { return false; }
+  bool rebuild_q_ok() const { return false; }
   long n5() const { return gv.nsites * Ls; }
 
   // out (5D parity p) = ax x + scale4 H4 in + r5 H5 in, in of parity 1 - p (dag: the adjoint
@@ -459,8 +472,9 @@ struct Op5 {
   }
   // S^dag q with the CG step fused into its last hop (see Op::mprec_dag_cg)
   void mprec_dag_cg(CHalf<P> in, Half<P> tmp_o, Half<P> tmp_e, Half<P> r, const double* scalars, double* partials,
-                    bool ready = false) const {
+                    bool ready = false, bool q_rebuilt = false) const {
     (void)tmp_e;
+    (void)q_rebuilt;
     (void)ready;
     K(1, in, tmp_o, true, 0.5, 1.0);
     K(0, cv(tmp_o), Half<P>{nullptr, nullptr}, true, -0.5 / d0, -1.0 / d0, in, d0, partials, r, scalars);

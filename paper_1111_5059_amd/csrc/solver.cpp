@@ -104,7 +104,9 @@ static int cg_normal(dwf_ctx* ctx, const OpT<P64>& op64, const OpT<Pi>& opi, CHa
   // inner vectors
   Half<Pi> r = hview<Pi>(MIXED ? ws_get(ctx, tag + ".r." + pname(Pi::ID), hbi) : (void*)rhi.data, g, Ls);
   if (!MIXED) r = hview<Pi>((void*)rhi.data, g, Ls);
-  Half<Pi> q = hview<Pi>(ws_get(ctx, tag + ".q." + pname(Pi::ID), hbi), g, Ls);
+  // q = M p is stored only where the last hop of M^dag q cannot rebuild it from A^-dag q
+  const bool OUT2 = opi.second_output_ok(), QREB = OUT2 && opi.rebuild_q_ok();
+  Half<Pi> q = QREB ? Half<Pi>{nullptr, nullptr} : hview<Pi>(ws_get(ctx, tag + ".q." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> te = hview<Pi>(ws_get(ctx, tag + ".te." + pname(Pi::ID), hbi), g, Ls);
   Half<Pi> to = hview<Pi>(ws_get(ctx, tag + ".to." + pname(Pi::ID), hbi), g, Ls);
   Half<PX> xl = hview<PX>(MIXED ? ws_get(ctx, tag + ".xlo", half_size<PX>(g, Ls)) : (void*)x.data, g, Ls);
@@ -146,13 +148,13 @@ static int cg_normal(dwf_ctx* ctx, const OpT<P64>& op64, const OpT<Pi>& opi, CHa
   // p = r
   p_update(0.0, rr);
   double rr_max = rr, rr_true = rr;
-  const bool OUT2 = opi.second_output_ok();
   const long nb_hop = opi.hop_blocks();
   int it = 0;
   while (it < maxit) {
     const Half<Pi> p = pr[cur];
     // q = M p, |q|^2 -> alpha = rr / |q|^2 (also kept in the history slot of this direction)
-    // (with A^-dag q, the first step of M^dag q, as a second output of the last hop)
+    // (with A^-dag q, the first step of M^dag q, as a second output of the last hop, and then,
+    // where the last hop of M^dag q rebuilds q from it, q itself is not stored)
     const Half<Pi> q2 = OUT2 ? to : Half<Pi>{nullptr, nullptr};
     if (PRE) opi.mprec_pre(cv(fp), cv(p), q, te, part, q2);
     else opi.mprec(cv(p), q, te, part, q2);
@@ -161,7 +163,7 @@ static int cg_normal(dwf_ctx* ctx, const OpT<P64>& op64, const OpT<Pi>& opi, CHa
     pend.slot[pend.n] = pend.n;
     ++pend.n;
     // r -= alpha M^dag q and |r|^2, fused into the last hop of M^dag q
-    opi.mprec_dag_cg(cv(q), to, te, r, sc, part, OUT2);
+    opi.mprec_dag_cg(cv(q), to, te, r, sc, part, OUT2, QREB);
     DWF_CHECK_LAUNCH(launch_reduce(part, int(nb_hop), 1, sc, S_RRNEW, 0, s));
     if (pend.n == KX) flush();
     double rr_new = read_scalar(ctx, sc, S_RRNEW);
@@ -498,7 +500,8 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
   double* part = reinterpret_cast<double*>(ws_get(ctx, "ilv.partials", size_t(K0) * pstride * sizeof(double)));
   double* sc = reinterpret_cast<double*>(ws_get(ctx, "ilv.scalars", size_t(K0) * S_COUNT * sizeof(double)));
   double* dcoef = reinterpret_cast<double*>(ws_get(ctx, "ilv.coef", size_t(2) * K0 * sizeof(double)));
-  const size_t nscan = size_t(3) * K0;
+  // the fifth-dimension tables per right-hand side: A^-1, A^-dag, A^-dag (F^dag), A^dag
+  const size_t nscan = size_t(4) * K0;
   FifthScan<R>* dscan = reinterpret_cast<FifthScan<R>*>(ws_get(ctx, "ilv.scan", nscan * sizeof(FifthScan<R>)));
   // pinned host mirrors: scalars, p-update coefficients, fifth-dimension tables (freed on every
   // exit, also when a later allocation throws)
@@ -518,7 +521,9 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
   // interleaved inner vectors (sized for all K0 right-hand sides)
   const size_t hbi = half_bytes<Pi>(ns, LT0);
   void* rb = ws_get(ctx, "ilv.r", hbi);
-  void* qb = ws_get(ctx, "ilv.q", hbi);
+  // q = M p is rebuilt by the last hop from A^-dag q (as in cg_normal), except in FP64
+  constexpr bool QREB = MIXED;
+  void* qb = QREB ? nullptr : ws_get(ctx, "ilv.q", hbi);
   void* teb = ws_get(ctx, "ilv.te", hbi);
   void* tob = ws_get(ctx, "ilv.to", hbi);
   void* pb[KX];
@@ -580,6 +585,7 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
       hscan[0 * K0 + r] = o.es[E_AINV];
       hscan[1 * K0 + r] = o.es[E_AINVDAG];
       hscan[2 * K0 + r] = o.es[E_AINVDAG_FDAG];
+      hscan[3 * K0 + r] = o.es[E_ADAG];
     }
     DWF_CHECK_HIP(hipMemcpyAsync(dscan, hscan, nscan * sizeof(FifthScan<R>), hipMemcpyHostToDevice, s));
   };
@@ -619,7 +625,7 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
     if (mark >= 0) {
       const double fb = spinor_site_bytes<Pi>();
       const bool xin = a.x.data != nullptr;
-      const double nb = a.cg_r.data ? 3 + (xin ? 1 : 0) : 2 + (xin ? 1 : 0) + (a.out2.data ? 1 : 0);
+      const double nb = a.cg_r.data ? 3 + (xin ? 1 : 0) : 1 + (a.out.data ? 1 : 0) + (xin ? 1 : 0) + (a.out2.data ? 1 : 0);
       timer_end(ctx, mark, double(ns) * LT * fb * nb + double(ns) * 72 * sizeof(SS));
     }
   };
@@ -645,7 +651,8 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
       h.nbr = g->d_nbr[out_par];
       h.order = g->d_order[out_par];
     };
-    const Half<Pi> p = H(pb[cur], LT), r = H(rb, LT), q = H(qb, LT), te = H(teb, LT), to = H(tob, LT);
+    const Half<Pi> p = H(pb[cur], LT), r = H(rb, LT), te = H(teb, LT), to = H(tob, LT);
+    const Half<Pi> q = QREB ? Half<Pi>{nullptr, nullptr} : H(qb, LT);
     HopArgs<Pi> h0, h1, h2, h3;
     base(h0, 0);  // te = A^-1 H_eo p
     h0.in = cv(p);
@@ -653,7 +660,7 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
     h0.scale = R(1);
     h0.epi_scan = 1;
     h0.es_tab = dscan;
-    base(h1, 1);  // q = p - 1/4 A^-1 H_oe te, |q|^2, and to = A^-dag q
+    base(h1, 1);  // q = p - 1/4 A^-1 H_oe te (stored in FP64 only), |q|^2, and to = A^-dag q
     h1.in = cv(te);
     h1.out = q;
     h1.scale = R(-0.25);
@@ -670,11 +677,15 @@ static void cg_batched_ilv(dwf_ctx* ctx, std::vector<BatchSys*> sys, double delt
     h2.scale = R(1);
     h2.epi_scan = 1;
     h2.es_tab = dscan + 2 * K0;
-    base(h3, 1);  // r -= alpha (q - 1/4 H^dag_oe te), |r|^2
+    base(h3, 1);  // r -= alpha (q - 1/4 H^dag_oe te), |r|^2 (q = A^dag to unless stored)
     h3.in = cv(te);
     h3.out = Half<Pi>{nullptr, nullptr};
     h3.scale = R(-0.25);
-    h3.x = cv(q);
+    h3.x = QREB ? cv(to) : cv(q);
+    if (QREB) {
+      h3.x_es2 = 1;
+      h3.es2_tab = dscan + 3 * K0;
+    }
     h3.ax = R(1);
     h3.norm_partials = part;
     h3.cg_r = r;
