@@ -112,6 +112,34 @@ def test_partial_cg_iterates_at_bench_extents(env, ora, Ls, b, c, m, k):
     assert abs(info["true_rel_resid"] - info_o["true_rel_resid"]) < 1e-9 * info_o["true_rel_resid"]
 
 
+# k iterations of CG with FP32/FP16/BF16 stored fields against the exact CGNR iterate: each stored
+# field carries a relative rounding of the storage unit roundoff u (2^-24, 2^-11, 2^-8) per iteration,
+# so the iterate stays within a modest multiple of k u of the exact one (bound 10 k u; about 1-3 u
+# measured)
+LOW_PREC_U = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("Ls,b,c,m", SYSTEMS)
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_partial_cg_iterates_low_precision(env, ora, Ls, b, c, m, prec):
+    """The mixed-precision CG after k = 3 iterations (where q = M_prec p is not stored: the last hop
+    of M_prec^dag q rebuilds it from A^-dag q) follows the oracle's CGNR iterates to the storage
+    precision; a wrong rebuild changes the direction and the iterate at O(1)."""
+    dwf, ctx = env
+    k = 3
+    U, src = system(DIMS, Ls, 40 + Ls)
+    po = ora.params(DIMS, Ls, M5=1.8, mass=m, b=b, c=c)
+    xo, info_o = ora.solve(po, U, src, tol=1e-14, maxit=k)
+    lat = dwf.Lattice(ctx, DIMS, Ls, M5=1.8, mass=m, b=b, c=c)
+    Ug, bg, xg = lat.pack_gauge(U), lat.pack(src), lat.zeros(dwf.KIND_FULL)
+    info = dwf.cg_ne(ctx, lat.params(prec_inner=dwf.PREC_NAMES[prec]), Ug, bg, xg, tol=1e-14, maxit=k)
+    record(dwf, ctx, f"partial cg {prec} Ls={Ls} b={b}")
+    assert info["iters"] == k and not info["converged"], info
+    err = rel_err(lat.unpack_np(xg), xo)
+    print(prec, Ls, b, err)
+    assert err < 10 * k * LOW_PREC_U[prec]
+
+
 @pytest.mark.parametrize("b,c,m", [(1.0, 0.0, 0.005), (1.5, 0.5, 0.005), (1.0, 0.0, 1.0)])
 def test_fp64_operators_at_Ls32(env, ora, b, c, m):
     """D(m), A, A^-1, M_prec and their adjoints in FP64 at Ls = 32 (the operators of the
