@@ -184,8 +184,11 @@ int dwf_dslash_noalloc(dwf_ctx* ctx, const dwf_params* p, const void* U, const v
  * storage precision (FP32 arithmetic) with FP64 reliable updates, FP64 CG
  * scalars and an FP64 solution accumulator.  Workspace (held by ctx from the
  * first call until dwf_ctx_destroy): eight search directions, the residual and
- * three temporaries as odd half fields of the iteration precision (one more for
- * Moebius operators), an FP32 solution increment and eleven FP64 half fields
+ * two temporaries as odd half fields of the iteration precision (one more for
+ * Moebius operators, and one more, M_prec p, for FP64 iterations, s-dependent
+ * coefficients, Ls other than 8, 16, 32, and launch shapes with several slices per
+ * thread or LDS-staged neighbours: elsewhere the last hop of M_prec^+ q rebuilds q
+ * from A^-+ q), an FP32 solution increment and eleven FP64 half fields
  * (one FP64 half field at 24^3x64, Ls = 32: 2.7 GB; the whole set in FP16
  * iterations about 40 GB). */
 int cg_ne(dwf_ctx* ctx, const dwf_params* p, const void* U, const void* b, void* x, dwf_solve_info* info);
