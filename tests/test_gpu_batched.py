@@ -148,6 +148,38 @@ def test_bf16_interleaved_ladder(env, ora):
         assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(srcs[k]), (k, m)
 
 
+# storage unit roundoff of the iteration precisions (see test_partial_cg_iterates_low_precision)
+LOW_PREC_U = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_interleaved_iterates_follow_cgnr(env, ora, prec):
+    """A four-mass Shamir ladder at Ls = 16 runs interleaved, where the last stage rebuilds each
+    right-hand side's q = M_prec p from A^-dag q with that right-hand side's A^dag; after k = 3
+    iterations every iterate is the oracle's CGNR iterate for its mass to within 10 k u."""
+    dwf, ctx = env
+    dims, Ls, k = (4, 4, 4, 8), 16, 3
+    masses = [0.005, 0.02, 0.1, 0.4]
+    U = synth.random_links(dims, 0.6, 1561)
+    lat = dwf.Lattice(ctx, dims, Ls, M5=1.8)
+    Ug = lat.pack_gauge(U)
+    P = dwf.PREC_NAMES[prec]
+    pars, bs, xs, srcs = [], [], [], []
+    for j, m in enumerate(masses):
+        b = synth.gaussian_spinor(dims, Ls, 1570 + j)
+        srcs.append(b)
+        pars.append(lat.params(mass=m, prec_inner=P))
+        bs.append(lat.pack(b))
+        xs.append(lat.zeros(dwf.KIND_FULL))
+    infos = dwf.cg_ne_batched(ctx, pars, Ug, bs, xs, tol=1e-14, maxit=k)
+    for j, (info, m) in enumerate(zip(infos, masses)):
+        assert info["iters"] == k and not info["converged"], (j, info)
+        xo, info_o = ora.solve(ora.params(dims, Ls, M5=1.8, mass=m), U, srcs[j], tol=1e-14, maxit=k)
+        err = rel_err(lat.unpack_np(xs[j]), xo)
+        print(prec, m, err)
+        assert err < 10 * k * LOW_PREC_U[prec], (j, m, err)
+
+
 def test_batch_beyond_one_launch(env, ora):
     """Nine Shamir right-hand sides at Ls = 32: the interleaved hop takes at most 256 / Ls = 8 per
     launch, so they run as a chunk of 8 and a chunk of 1; a tenth at Ls = 12 (no interleaved form) in
